@@ -1,0 +1,405 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct FP64 CPU reference for the
+ * stencil hot path (horizontal diffusion, implicit vertical advection, their
+ * time step and the hand-derived adjoints).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * Sources:
+ *   - Semantics of a stencil call (GT4Py paper, Sec. 2.2): the horizontal
+ *     plane is always parallel; vertical computations run PARALLEL, FORWARD
+ *     or BACKWARD; intervals specialise boundary levels; an assignment is
+ *     evaluated over the whole domain before it is stored (so the output
+ *     never aliases the input); temporaries are not observable; the
+ *     iteration space comes from domain/origin.
+ *   - The two benchmark stencils named in Sec. 3.1 (Fig. 3): the multi-stage
+ *     horizontal diffusion and the vertical advection implicit solver.  The
+ *     formulas below are the benchmark definitions of those two stencils:
+ *       lap  = 4u - u[i-1] - u[i+1] - u[j-1] - u[j+1]
+ *       flx  = lap[i+1] - lap[i], zeroed where flx * (u[i+1]-u[i]) > 0
+ *       fly  = the same along j
+ *       out  = u - coeff * (flx - flx[i-1] + fly - fly[j-1])
+ *     and, per column with r = dt/dz,
+ *       a_k = -r/4 * w_k (k >= 1),  c_k = +r/4 * w_{k+1} (k <= nk-2),
+ *       a_0 = c_{nk-1} = 0,  b_k = 1 + |a_k| + |c_k|,  d_k = u_k + data_k,
+ *     solved by the Thomas algorithm (FORWARD elimination, BACKWARD
+ *     substitution).
+ *
+ * Array conventions (C order, all strides implied by the sizes):
+ *   padded  u, out, ubar : [nk][nj+4][ni+4], U(i,j,k) = u[k][j+2][i+2],
+ *                          i in [-2, ni+2), j in [-2, nj+2)
+ *   interior data, x, lam, xbar : [nk][nj][ni]
+ *   staggered w          : [nk+1][nj][ni]
+ *   masks (1 = flux kept, 0 = limiter zeroed it)
+ *     mx : [nk][nj][ni+1],  MX(i,j,k) = mx[k][j][i+1], i in [-1, ni)
+ *          flux between (i,j) and (i+1,j)
+ *     my : [nk][nj+1][ni],  MY(i,j,k) = my[k][j+1][i], j in [-1, nj)
+ *          flux between (i,j) and (i,j+1)
+ *
+ * Limiter decision precision: `decide_f32 == 0` takes the limiter decision in
+ * FP64; `decide_f32 != 0` computes lap, the flux difference and the gradient
+ * used *for the decision only* in IEEE binary32 with the same association,
+ * so that a binary32 implementation and this reference branch identically.
+ * All values are always carried in FP64.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* indexing helpers                                                     */
+/* ------------------------------------------------------------------ */
+#define PAD 2
+#define UIDX(i, j, k) ((size_t)(k) * (size_t)(nj + 2 * PAD) * (size_t)(ni + 2 * PAD) + \
+                       (size_t)((j) + PAD) * (size_t)(ni + 2 * PAD) + (size_t)((i) + PAD))
+#define IIDX(i, j, k) ((size_t)(k) * (size_t)nj * (size_t)ni + (size_t)(j) * (size_t)ni + (size_t)(i))
+#define MXIDX(i, j, k) ((size_t)(k) * (size_t)nj * (size_t)(ni + 1) + (size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1))
+#define MYIDX(i, j, k) ((size_t)(k) * (size_t)(nj + 1) * (size_t)ni + (size_t)((j) + 1) * (size_t)ni + (size_t)(i))
+
+/* The limiter (benchmark definition, Sec. 3.1): the flux is zeroed where
+ * flux * gradient > 0.  Evaluated as a sign test, which equals the product
+ * test in exact arithmetic and cannot be disturbed by underflow of f*g. */
+static int limiter_keeps(double f, double g) {
+  int zeroed = (f > 0.0 && g > 0.0) || (f < 0.0 && g < 0.0);
+  return !zeroed;
+}
+static int limiter_keeps_f32(float f, float g) {
+  int zeroed = (f > 0.0f && g > 0.0f) || (f < 0.0f && g < 0.0f);
+  return !zeroed;
+}
+
+/* Laplacian stage, fixed association: 4u - ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])). */
+static double lap64(const double* u, int ni, int nj, int i, int j, int k) {
+  double s = (u[UIDX(i - 1, j, k)] + u[UIDX(i + 1, j, k)]) +
+             (u[UIDX(i, j - 1, k)] + u[UIDX(i, j + 1, k)]);
+  return 4.0 * u[UIDX(i, j, k)] - s;
+}
+static float lap32(const double* u, int ni, int nj, int i, int j, int k) {
+  float s = ((float)u[UIDX(i - 1, j, k)] + (float)u[UIDX(i + 1, j, k)]) +
+            ((float)u[UIDX(i, j - 1, k)] + (float)u[UIDX(i, j + 1, k)]);
+  return 4.0f * (float)u[UIDX(i, j, k)] - s;
+}
+
+/* ------------------------------------------------------------------ */
+/* Limiter masks of the horizontal diffusion (Sec. 3.1 benchmark)        */
+/* ------------------------------------------------------------------ */
+void oracle_hdiff_masks(int ni, int nj, int nk, const double* u, int decide_f32,
+                        unsigned char* mx, unsigned char* my) {
+  for (int k = 0; k < nk; ++k) {
+    /* x-fluxes on [-1, ni) x [0, nj) */
+    for (int j = 0; j < nj; ++j)
+      for (int i = -1; i < ni; ++i) {
+        int keep;
+        if (decide_f32) {
+          float f = lap32(u, ni, nj, i + 1, j, k) - lap32(u, ni, nj, i, j, k);
+          float g = (float)u[UIDX(i + 1, j, k)] - (float)u[UIDX(i, j, k)];
+          keep = limiter_keeps_f32(f, g);
+        } else {
+          double f = lap64(u, ni, nj, i + 1, j, k) - lap64(u, ni, nj, i, j, k);
+          double g = u[UIDX(i + 1, j, k)] - u[UIDX(i, j, k)];
+          keep = limiter_keeps(f, g);
+        }
+        mx[MXIDX(i, j, k)] = (unsigned char)keep;
+      }
+    /* y-fluxes on [0, ni) x [-1, nj) */
+    for (int j = -1; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        int keep;
+        if (decide_f32) {
+          float f = lap32(u, ni, nj, i, j + 1, k) - lap32(u, ni, nj, i, j, k);
+          float g = (float)u[UIDX(i, j + 1, k)] - (float)u[UIDX(i, j, k)];
+          keep = limiter_keeps_f32(f, g);
+        } else {
+          double f = lap64(u, ni, nj, i, j + 1, k) - lap64(u, ni, nj, i, j, k);
+          double g = u[UIDX(i, j + 1, k)] - u[UIDX(i, j, k)];
+          keep = limiter_keeps(f, g);
+        }
+        my[MYIDX(i, j, k)] = (unsigned char)keep;
+      }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Horizontal diffusion with the limiter masks given: the four stages   */
+/* lap -> flx -> fly -> out, evaluated stage by stage over the whole    */
+/* level (Sec. 2.2: each assignment covers the full domain first).      */
+/* With masks taken from the same u this is the forward stencil; with   */
+/* masks held fixed it is its (a.e.) tangent-linear map.                */
+/* Writes the interior of `out` only (out[k][j][i], interior layout).   */
+/* ------------------------------------------------------------------ */
+static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coeff,
+                             const unsigned char* mx, const unsigned char* my,
+                             double* out_interior) {
+  const int li = ni + 2, lj = nj + 2; /* lap on the box [-1,ni] x [-1,nj] */
+  double* lap = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
+  double* fx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)nj);
+  double* fy = (double*)malloc(sizeof(double) * (size_t)ni * (size_t)(nj + 1));
+#define LAP(i, j) lap[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)]
+#define FX(i, j) fx[(size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1)]
+#define FY(i, j) fy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)]
+  for (int k = 0; k < nk; ++k) {
+    for (int j = -1; j <= nj; ++j)
+      for (int i = -1; i <= ni; ++i) LAP(i, j) = lap64(u, ni, nj, i, j, k);
+    for (int j = 0; j < nj; ++j)
+      for (int i = -1; i < ni; ++i) {
+        double f = LAP(i + 1, j) - LAP(i, j);
+        FX(i, j) = mx[MXIDX(i, j, k)] ? f : 0.0;
+      }
+    for (int j = -1; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        double f = LAP(i, j + 1) - LAP(i, j);
+        FY(i, j) = my[MYIDX(i, j, k)] ? f : 0.0;
+      }
+    for (int j = 0; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        double div = (FX(i, j) - FX(i - 1, j)) + (FY(i, j) - FY(i, j - 1));
+        out_interior[IIDX(i, j, k)] = u[UIDX(i, j, k)] - coeff * div;
+      }
+  }
+#undef LAP
+#undef FX
+#undef FY
+  free(lap);
+  free(fx);
+  free(fy);
+}
+
+/* Forward horizontal diffusion.  `out` is padded: interior = the update,
+ * halo = a copy of u's halo (the halo is never computed, only carried). */
+void oracle_hdiff(int ni, int nj, int nk, const double* u, double coeff, int decide_f32,
+                  double* out, unsigned char* mx, unsigned char* my) {
+  oracle_hdiff_masks(ni, nj, nk, u, decide_f32, mx, my);
+  double* h = (double*)malloc(sizeof(double) * (size_t)ni * (size_t)nj * (size_t)nk + 8);
+  hdiff_with_masks(ni, nj, nk, u, coeff, mx, my, h);
+  memcpy(out, u, sizeof(double) * (size_t)(ni + 4) * (size_t)(nj + 4) * (size_t)nk);
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) out[UIDX(i, j, k)] = h[IIDX(i, j, k)];
+  free(h);
+}
+
+/* ------------------------------------------------------------------ */
+/* Vertical advection (Sec. 3.1 benchmark): tridiagonal system per      */
+/* column; the boundary rows (intervals, Sec. 2.2) have a_0 = 0 and     */
+/* c_{nk-1} = 0.  Thomas algorithm: FORWARD elimination then BACKWARD   */
+/* substitution (Sec. 2.2 vertical iteration orders).                   */
+/* ------------------------------------------------------------------ */
+static double coef_a(const double* w, int ni, int nj, int i, int j, int k, double r) {
+  (void)nj;
+  return k >= 1 ? (-0.25 * r) * w[(size_t)k * (size_t)nj * (size_t)ni + (size_t)j * (size_t)ni + (size_t)i] : 0.0;
+}
+static double coef_c(const double* w, int ni, int nj, int nk, int i, int j, int k, double r) {
+  return k <= nk - 2 ? (0.25 * r) * w[(size_t)(k + 1) * (size_t)nj * (size_t)ni + (size_t)j * (size_t)ni + (size_t)i] : 0.0;
+}
+
+/* x = T^{-1} d per column, d[k] given (interior layout). */
+static void thomas_columns(int ni, int nj, int nk, const double* d, const double* w, double dt_dz,
+                           double* x) {
+  double* cp = (double*)malloc(sizeof(double) * (size_t)nk + 8);
+  double* dp = (double*)malloc(sizeof(double) * (size_t)nk + 8);
+  for (int j = 0; j < nj; ++j)
+    for (int i = 0; i < ni; ++i) {
+      for (int k = 0; k < nk; ++k) {
+        double a = coef_a(w, ni, nj, i, j, k, dt_dz);
+        double c = coef_c(w, ni, nj, nk, i, j, k, dt_dz);
+        double b = 1.0 + fabs(a) + fabs(c);
+        double dk = d[IIDX(i, j, k)];
+        if (k == 0) {
+          cp[0] = c / b;
+          dp[0] = dk / b;
+        } else {
+          double m = b - a * cp[k - 1];
+          cp[k] = c / m;
+          dp[k] = (dk - a * dp[k - 1]) / m;
+        }
+      }
+      x[IIDX(i, j, nk - 1)] = dp[nk - 1];
+      for (int k = nk - 2; k >= 0; --k) x[IIDX(i, j, k)] = dp[k] - cp[k] * x[IIDX(i, j, k + 1)];
+    }
+  free(cp);
+  free(dp);
+}
+
+/* vadv alone: right-hand side d = u_in + data, all interior layout. */
+void oracle_vadv(int ni, int nj, int nk, const double* uin, const double* data, const double* w,
+                 double dt_dz, double* x) {
+  if (ni <= 0 || nj <= 0 || nk <= 0) return;
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  double* d = (double*)malloc(sizeof(double) * n);
+  for (size_t p = 0; p < n; ++p) d[p] = uin[p] + data[p];
+  thomas_columns(ni, nj, nk, d, w, dt_dz, x);
+  free(d);
+}
+
+/* One time step: horizontal diffusion, then vertical advection with the
+ * diffused field as u_k in d_k = u_k + data_k.  `next` is padded: interior
+ * = x, halo = u's halo (held fixed). */
+void oracle_step(int ni, int nj, int nk, const double* u, const double* data, const double* w,
+                 double coeff, double dt_dz, int decide_f32, double* next, unsigned char* mx,
+                 unsigned char* my) {
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  memcpy(next, u, sizeof(double) * (size_t)(ni + 4) * (size_t)(nj + 4) * (size_t)nk);
+  if (n == 0) return;
+  oracle_hdiff_masks(ni, nj, nk, u, decide_f32, mx, my);
+  double* h = (double*)malloc(sizeof(double) * n);
+  double* x = (double*)malloc(sizeof(double) * n);
+  hdiff_with_masks(ni, nj, nk, u, coeff, mx, my, h);
+  for (size_t p = 0; p < n; ++p) h[p] += data[p];
+  thomas_columns(ni, nj, nk, h, w, dt_dz, x);
+  for (int k = 0; k < nk; ++k)
+    for (int j = 0; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) next[UIDX(i, j, k)] = x[IIDX(i, j, k)];
+  free(h);
+  free(x);
+}
+
+/* ------------------------------------------------------------------ */
+/* Adjoints (transpose of the a.e. Jacobian, limiter masks held fixed)  */
+/* ------------------------------------------------------------------ */
+
+/* Horizontal diffusion adjoint: ubar = J_h^T lam over the whole padded
+ * domain.  lam is given on the interior and is zero outside it. */
+void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsigned char* mx,
+                          const unsigned char* my, double coeff, double* ubar) {
+  const int li = ni + 2, lj = nj + 2;
+  double* gx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)(nj > 0 ? nj : 1));
+  double* gy = (double*)malloc(sizeof(double) * (size_t)(ni > 0 ? ni : 1) * (size_t)(nj + 1));
+  double* lb = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
+#define LAM(i, j) (((i) >= 0 && (i) < ni && (j) >= 0 && (j) < nj) ? lam[IIDX(i, j, k)] : 0.0)
+#define GX(i, j) ((((i) >= -1 && (i) < ni && (j) >= 0 && (j) < nj)) ? gx[(size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1)] : 0.0)
+#define GY(i, j) ((((i) >= 0 && (i) < ni && (j) >= -1 && (j) < nj)) ? gy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)] : 0.0)
+#define LB(i, j) ((((i) >= -1 && (i) <= ni && (j) >= -1 && (j) <= nj)) ? lb[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)] : 0.0)
+  for (int k = 0; k < nk; ++k) {
+    /* out(p) = u(p) - coeff * (Fx(p) - Fx(p-ei) + Fy(p) - Fy(p-ej)):
+     * dout(p)/dFx(q) = -coeff if q == p, +coeff if q == p - ei.
+     * Fx(q) = MX(q) * (lap(q+ei) - lap(q)). Keep the masked flux cotangent. */
+    for (int j = 0; j < nj; ++j)
+      for (int i = -1; i < ni; ++i) {
+        double fbar = -coeff * (LAM(i, j) - LAM(i + 1, j));
+        gx[(size_t)j * (size_t)(ni + 1) + (size_t)(i + 1)] = mx[MXIDX(i, j, k)] ? fbar : 0.0;
+      }
+    for (int j = -1; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        double fbar = -coeff * (LAM(i, j) - LAM(i, j + 1));
+        gy[(size_t)(j + 1) * (size_t)ni + (size_t)i] = my[MYIDX(i, j, k)] ? fbar : 0.0;
+      }
+    /* lap(q) enters Fx(q-ei) with +1 and Fx(q) with -1 (same for y). */
+    for (int j = -1; j <= nj; ++j)
+      for (int i = -1; i <= ni; ++i)
+        lb[(size_t)(j + 1) * (size_t)li + (size_t)(i + 1)] =
+            (GX(i - 1, j) - GX(i, j)) + (GY(i, j - 1) - GY(i, j));
+    /* lap(q) = 4u(q) - u(q+-ei) - u(q+-ej); plus the identity term of out. */
+    for (int j = -2; j < nj + 2; ++j)
+      for (int i = -2; i < ni + 2; ++i) {
+        double v = LAM(i, j) + 4.0 * LB(i, j) - LB(i + 1, j) - LB(i - 1, j) - LB(i, j + 1) -
+                   LB(i, j - 1);
+        ubar[UIDX(i, j, k)] = v;
+      }
+  }
+#undef LAM
+#undef GX
+#undef GY
+#undef LB
+  free(gx);
+  free(gy);
+  free(lb);
+}
+
+/* Vertical advection adjoint: lam = T^{-T} xbar.  T^T has sub-diagonal
+ * c_{k-1}, diagonal b_k and super-diagonal a_{k+1}; solved by a fresh
+ * Thomas elimination on that transposed matrix. */
+void oracle_vadv_adjoint(int ni, int nj, int nk, const double* xbar, const double* w, double dt_dz,
+                         double* lam) {
+  if (ni <= 0 || nj <= 0 || nk <= 0) return;
+  double* al = (double*)malloc(sizeof(double) * (size_t)nk);
+  double* be = (double*)malloc(sizeof(double) * (size_t)nk);
+  for (int j = 0; j < nj; ++j)
+    for (int i = 0; i < ni; ++i) {
+      for (int k = 0; k < nk; ++k) {
+        double sub = k >= 1 ? coef_c(w, ni, nj, nk, i, j, k - 1, dt_dz) : 0.0;
+        double sup = k <= nk - 2 ? coef_a(w, ni, nj, i, j, k + 1, dt_dz) : 0.0;
+        double ak = coef_a(w, ni, nj, i, j, k, dt_dz);
+        double ck = coef_c(w, ni, nj, nk, i, j, k, dt_dz);
+        double diag = 1.0 + fabs(ak) + fabs(ck);
+        double rhs = xbar[IIDX(i, j, k)];
+        if (k == 0) {
+          al[0] = sup / diag;
+          be[0] = rhs / diag;
+        } else {
+          double m = diag - sub * al[k - 1];
+          al[k] = sup / m;
+          be[k] = (rhs - sub * be[k - 1]) / m;
+        }
+      }
+      lam[IIDX(i, j, nk - 1)] = be[nk - 1];
+      for (int k = nk - 2; k >= 0; --k) lam[IIDX(i, j, k)] = be[k] - al[k] * lam[IIDX(i, j, k + 1)];
+    }
+  free(al);
+  free(be);
+}
+
+/* Step adjoint: lam = T^{-T} xbar; ubar = J_h^T lam; databar = lam. */
+void oracle_step_adjoint(int ni, int nj, int nk, const double* xbar, const double* w,
+                         const unsigned char* mx, const unsigned char* my, double coeff,
+                         double dt_dz, double* ubar, double* databar) {
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  double* lam = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  oracle_vadv_adjoint(ni, nj, nk, xbar, w, dt_dz, lam);
+  oracle_hdiff_adjoint(ni, nj, nk, lam, mx, my, coeff, ubar);
+  if (databar) memcpy(databar, lam, sizeof(double) * n);
+  free(lam);
+}
+
+/* Tangent-linear step with masks held fixed: dx = T^{-1} (J_h v). `v` is
+ * padded, `dx` interior.  No forcing term (data enters additively). */
+void oracle_step_tangent(int ni, int nj, int nk, const double* v, const double* w,
+                         const unsigned char* mx, const unsigned char* my, double coeff,
+                         double dt_dz, double* dx) {
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  if (n == 0) return;
+  double* h = (double*)malloc(sizeof(double) * n);
+  hdiff_with_masks(ni, nj, nk, v, coeff, mx, my, h);
+  thomas_columns(ni, nj, nk, h, w, dt_dz, dx);
+  free(h);
+}
+
+/* Tangent of the horizontal diffusion alone (interior output). */
+void oracle_hdiff_tangent(int ni, int nj, int nk, const double* v, const unsigned char* mx,
+                          const unsigned char* my, double coeff, double* dh) {
+  if ((size_t)ni * (size_t)nj * (size_t)nk == 0) return;
+  hdiff_with_masks(ni, nj, nk, v, coeff, mx, my, dh);
+}
+
+/* Tridiagonal matrix-vector product y = T x per column (for residual pins). */
+void oracle_tridiag_apply(int ni, int nj, int nk, const double* x, const double* w, double dt_dz,
+                          double* y) {
+  for (int j = 0; j < nj; ++j)
+    for (int i = 0; i < ni; ++i)
+      for (int k = 0; k < nk; ++k) {
+        double a = coef_a(w, ni, nj, i, j, k, dt_dz);
+        double c = coef_c(w, ni, nj, nk, i, j, k, dt_dz);
+        double b = 1.0 + fabs(a) + fabs(c);
+        double v = b * x[IIDX(i, j, k)];
+        if (k >= 1) v += a * x[IIDX(i, j, k - 1)];
+        if (k <= nk - 2) v += c * x[IIDX(i, j, k + 1)];
+        y[IIDX(i, j, k)] = v;
+      }
+}
+
+/* The Laplacian stage alone on the box [-1, ni] x [-1, nj]:
+ * lap[k][j+1][i+1], shape [nk][nj+2][ni+2]. */
+void oracle_laplacian(int ni, int nj, int nk, const double* u, double* lap) {
+  for (int k = 0; k < nk; ++k)
+    for (int j = -1; j <= nj; ++j)
+      for (int i = -1; i <= ni; ++i)
+        lap[(size_t)k * (size_t)(nj + 2) * (size_t)(ni + 2) + (size_t)(j + 1) * (size_t)(ni + 2) +
+            (size_t)(i + 1)] = lap64(u, ni, nj, i, j, k);
+}
+
+int oracle_version(void) { return 1; }

@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against facts fixed by the mathematics.
+
+Every check here is independent of the oracle's own code path: closed forms
+derived by hand from the benchmark stencils of Sec. 3.1 (fixtures under
+``tests/golden/``), invariants, dense library solves of small systems,
+brute-force Jacobians and finite differences.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle_py
+from paper_2311_08322_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+COEFF = inputs.COEFF
+DT_DZ = inputs.DT_DZ
+
+
+def _grid(ni, nj, nk):
+    """Interior-relative (i, j) index arrays on the padded (nk, nj+4, ni+4) grid."""
+    i = np.arange(-2, ni + 2, dtype=np.float64)
+    j = np.arange(-2, nj + 2, dtype=np.float64)
+    J, I = np.meshgrid(j, i, indexing="ij")
+    return (np.broadcast_to(I, (nk,) + I.shape).copy(), np.broadcast_to(J, (nk,) + J.shape).copy())
+
+
+def _interior(a):
+    return a[:, 2:-2, 2:-2]
+
+
+def _golden(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _case(doc, name):
+    return next(c for c in doc["cases"] if c["name"] == name)
+
+
+# ---------------------------------------------------------------- P1-P5
+def test_p1_laplacian_of_quadratic_is_constant(oracle):
+    c = _case(_golden("hdiff_closed_forms.json"), "quadratic")
+    I, J = _grid(9, 7, 2)
+    u = c["A"] * I**2 + c["B"] * J**2 + c["C"] * I * J + c["D"] * I + c["E"] * J + c["F"]
+    lap = oracle.laplacian(u)
+    assert lap.shape == (2, 9, 11)
+    assert np.all(lap == c["lap"])
+    # a quadratic has constant lap, so every flux difference is zero: out == u
+    out, _, _ = oracle.hdiff(u, COEFF)
+    assert np.array_equal(out, u)
+
+
+def test_p2_constant_field_is_not_diffused(oracle):
+    u = np.full((3, 10, 12), 0.7353)
+    out, mx, my = oracle.hdiff(u, COEFF)
+    assert np.array_equal(out, u)
+    # zero flux ties count as kept (strict > 0 zeroes)
+    assert mx.all() and my.all()
+    # with w = 0 the tridiagonal matrix is the identity and data = 0
+    nk, nj, ni = 3, 6, 8
+    nxt, _, _ = oracle.step(u, np.zeros((nk, nj, ni)), np.zeros((nk + 1, nj, ni)), COEFF, DT_DZ)
+    assert np.array_equal(nxt, u)
+
+
+def test_p3_linear_field_has_zero_laplacian(oracle):
+    I, J = _grid(8, 6, 3)
+    u = 2.0 * I - 3.0 * J + 5.0
+    assert np.all(oracle.laplacian(u) == 0.0)
+    out, _, _ = oracle.hdiff(u, COEFF)
+    assert np.array_equal(out, u)
+
+
+def test_p4_checkerboard_limiter_zeroes_every_x_flux(oracle):
+    c = _case(_golden("hdiff_closed_forms.json"), "checkerboard in i")
+    I, _ = _grid(10, 6, 2)
+    u = np.where(I.astype(np.int64) % 2 == 0, 1.0, -1.0)
+    out, mx, my = oracle.hdiff(u, c["coeff"])
+    assert not mx.any(), "every x-flux has the sign of the gradient and must be zeroed"
+    assert my.all(), "y-fluxes are zero (ties) and kept"
+    assert np.array_equal(out, u * c["limited_factor"])
+    # the same stencil with the limiter switched off (all masks 1)
+    ones_x = np.ones_like(mx)
+    ones_y = np.ones_like(my)
+    h = oracle.hdiff_tangent(u, ones_x, ones_y, c["coeff"])
+    np.testing.assert_allclose(h, _interior(u) * c["unlimited_factor"], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("axis", ["i", "j"])
+def test_p5_quartic_keeps_every_flux_and_adds_24_coeff(oracle, axis):
+    c = _case(_golden("hdiff_closed_forms.json"), "quartic in i")
+    ni, nj, nk = 9, 8, 2
+    I, J = _grid(ni, nj, nk)
+    x = (I if axis == "i" else J) + 4.0
+    u = x**4
+    out, mx, my = oracle.hdiff(u, c["coeff"])
+    if axis == "i":
+        assert mx.all()
+    else:
+        assert my.all()
+    d = _interior(out) - _interior(u)
+    np.testing.assert_allclose(d, c["increment"], rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------- P6
+def test_p6_limiter_predicate_on_random_field(oracle):
+    f = inputs.fields_sized(37, 29, 5, seed=7)
+    u = f.u
+    lap = oracle.laplacian(u)  # box [-1, ni] x [-1, nj]
+    mx, my = oracle.hdiff_masks(u)
+    # x-fluxes on [-1, ni) x [0, nj)
+    fx = lap[:, 1:-1, 1:] - lap[:, 1:-1, :-1]
+    gx = u[:, 2:-2, 2:-1] - u[:, 2:-2, 1:-2]
+    zeroed_x = fx * gx > 0
+    assert np.array_equal(mx == 0, zeroed_x)
+    fy = lap[:, 1:, 1:-1] - lap[:, :-1, 1:-1]
+    gy = u[:, 2:-1, 2:-2] - u[:, 1:-2, 2:-2]
+    zeroed_y = fy * gy > 0
+    assert np.array_equal(my == 0, zeroed_y)
+    # roughly 90% of the fluxes are zeroed on a U[0,1) field
+    frac = (zeroed_x.sum() + zeroed_y.sum()) / (zeroed_x.size + zeroed_y.size)
+    assert 0.8 < frac < 0.97
+
+
+def test_p6_f32_decisions_differ_only_at_near_ties(oracle):
+    f = inputs.fields_sized(64, 48, 6, seed=8)
+    u32 = f.u.astype(np.float32).astype(np.float64)
+    mx64, my64 = oracle.hdiff_masks(u32, decide_f32=False)
+    mx32, my32 = oracle.hdiff_masks(u32, decide_f32=True)
+    lap = oracle.laplacian(u32)
+    fx = lap[:, 1:-1, 1:] - lap[:, 1:-1, :-1]
+    bound_x = 64 * np.finfo(np.float32).eps * (np.abs(lap[:, 1:-1, 1:]) + np.abs(lap[:, 1:-1, :-1]))
+    diff = mx64 != mx32
+    assert np.all(np.abs(fx[diff]) <= bound_x[diff])
+    fy = lap[:, 1:, 1:-1] - lap[:, :-1, 1:-1]
+    bound_y = 64 * np.finfo(np.float32).eps * (np.abs(lap[:, 1:, 1:-1]) + np.abs(lap[:, :-1, 1:-1]))
+    diff = my64 != my32
+    assert np.all(np.abs(fy[diff]) <= bound_y[diff])
+
+
+# ---------------------------------------------------------------- P7-P9
+def _dense_T(wcol, dt_dz):
+    """Tridiagonal matrix of one column, written out from the definition."""
+    nk = len(wcol) - 1
+    T = np.zeros((nk, nk))
+    for k in range(nk):
+        a = -0.25 * dt_dz * wcol[k] if k >= 1 else 0.0
+        c = 0.25 * dt_dz * wcol[k + 1] if k <= nk - 2 else 0.0
+        T[k, k] = 1.0 + abs(a) + abs(c)
+        if k >= 1:
+            T[k, k - 1] = a
+        if k <= nk - 2:
+            T[k, k + 1] = c
+    return T
+
+
+def test_p7_thomas_residual_full_size(oracle):
+    wl = inputs.STEP_256
+    f = inputs.fields_for(wl)
+    d = _interior(f.u) + f.data
+    x = oracle.vadv(_interior(f.u), f.data, f.w, DT_DZ)
+    r = oracle.tridiag_apply(x, f.w, DT_DZ) - d
+    assert np.max(np.abs(r)) < 1e-13
+
+
+@pytest.mark.parametrize("nk", [1, 2, 3, 5, 8])
+def test_p8_dense_solve_agrees(oracle, nk):
+    f = inputs.fields_sized(5, 4, nk, seed=20 + nk)
+    uin = _interior(f.u)
+    x = oracle.vadv(uin, f.data, f.w, DT_DZ)
+    xb = inputs.cotangent(5, 4, nk, child=30 + nk)
+    lam = oracle.vadv_adjoint(xb, f.w, DT_DZ)
+    for j in range(4):
+        for i in range(5):
+            T = _dense_T(f.w[:, j, i], DT_DZ)
+            ref = np.linalg.solve(T, uin[:, j, i] + f.data[:, j, i])
+            np.testing.assert_allclose(x[:, j, i], ref, rtol=0, atol=1e-14)
+            refT = np.linalg.solve(T.T, xb[:, j, i])
+            np.testing.assert_allclose(lam[:, j, i], refT, rtol=0, atol=1e-14)
+
+
+def test_p9_zero_velocity_is_identity(oracle):
+    f = inputs.fields_sized(6, 5, 7, seed=40)
+    w0 = np.zeros_like(f.w)
+    uin = _interior(f.u)
+    x = oracle.vadv(uin, f.data, w0, DT_DZ)
+    assert np.array_equal(x, uin + f.data)
+    assert np.array_equal(oracle.vadv_adjoint(f.data, w0, DT_DZ), f.data)
+
+
+def _cramer(sub, diag, sup, d):
+    n = len(diag)
+    M = [[Fraction(0)] * n for _ in range(n)]
+    for k in range(n):
+        M[k][k] = Fraction(str(diag[k]))
+    for k in range(n - 1):
+        M[k + 1][k] = Fraction(str(sub[k]))
+        M[k][k + 1] = Fraction(str(sup[k]))
+
+    def det(A):
+        if len(A) == 1:
+            return A[0][0]
+        return sum((-1) ** c * A[0][c] * det([row[:c] + row[c + 1:] for row in A[1:]])
+                   for c in range(len(A)))
+
+    D = det(M)
+    xs = []
+    for c in range(n):
+        Mc = [row[:] for row in M]
+        for r in range(n):
+            Mc[r][c] = Fraction(str(d[r]))
+        xs.append(det(Mc) / D)
+    return xs
+
+
+def test_p9_hand_solved_columns(oracle):
+    doc = _golden("vadv_columns.json")
+    for case in doc["cases"]:
+        nk = case["nk"]
+        w = np.array(case["w"], dtype=np.float64).reshape(nk + 1, 1, 1)
+        d = np.array(case["d"], dtype=np.float64).reshape(nk, 1, 1)
+        x = oracle.vadv(d, np.zeros_like(d), w, case["dt_dz"])[:, 0, 0]
+        ref = _cramer(case["sub"], case["diag"], case["sup"], case["d"])
+        for k in range(nk):
+            assert abs(x[k] - float(ref[k])) <= 4e-16 * max(1.0, abs(float(ref[k]))), (case, k)
+        # the transposed system (adjoint) on the same hand matrix
+        lam = oracle.vadv_adjoint(d, w, case["dt_dz"])[:, 0, 0]
+        refT = _cramer(case["sup"], case["diag"], case["sub"], case["d"])
+        for k in range(nk):
+            assert abs(lam[k] - float(refT[k])) <= 4e-16 * max(1.0, abs(float(refT[k])))
+
+
+# ---------------------------------------------------------------- independent pure-Python copy
+def test_pure_python_copy_agrees(oracle):
+    f = inputs.fields_sized(6, 5, 3, seed=50)
+    out, mx, my = oracle.hdiff(f.u, COEFF)
+    out_py, mx_py, my_py = oracle_py.hdiff(f.u.tolist(), COEFF)
+    assert np.array_equal(mx, np.array(mx_py, np.uint8))
+    assert np.array_equal(my, np.array(my_py, np.uint8))
+    np.testing.assert_allclose(_interior(out), np.array(out_py), rtol=0, atol=1e-15)
+    uin = _interior(f.u)
+    x = oracle.vadv(uin, f.data, f.w, DT_DZ)
+    for j in range(5):
+        for i in range(6):
+            ref = oracle_py.thomas_column(list(uin[:, j, i] + f.data[:, j, i]), list(f.w[:, j, i]), DT_DZ)
+            np.testing.assert_allclose(x[:, j, i], ref, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P10-P12 (adjoint)
+def _brute_jacobian(fn, nin):
+    cols = []
+    for p in range(nin):
+        e = np.zeros(nin)
+        e[p] = 1.0
+        cols.append(fn(e).ravel())
+    return np.stack(cols, axis=1)
+
+
+def test_p10_step_adjoint_is_transpose_of_tangent(oracle):
+    ni, nj, nk = 5, 4, 3
+    f = inputs.fields_sized(ni, nj, nk, seed=60)
+    _, mx, my = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    shp = (nk, nj + 4, ni + 4)
+    J = _brute_jacobian(lambda e: oracle.step_tangent(e.reshape(shp), f.w, mx, my, COEFF, DT_DZ),
+                        int(np.prod(shp)))
+    ob = inputs.cotangent(ni, nj, nk, child=61)
+    ubar, dbar = oracle.step_adjoint(ob, f.w, mx, my, COEFF, DT_DZ)
+    np.testing.assert_allclose(ubar.ravel(), J.T @ ob.ravel(), rtol=0, atol=1e-14)
+    # d out / d data = T^{-1}: brute force through vadv with zero u_in
+    Jd = _brute_jacobian(lambda e: oracle.vadv(np.zeros((nk, nj, ni)), e.reshape(nk, nj, ni), f.w, DT_DZ),
+                         nk * nj * ni)
+    np.testing.assert_allclose(dbar.ravel(), Jd.T @ ob.ravel(), rtol=0, atol=1e-14)
+
+
+def test_p10_hdiff_adjoint_is_transpose_of_tangent(oracle):
+    ni, nj, nk = 6, 5, 2
+    f = inputs.fields_sized(ni, nj, nk, seed=62)
+    mx, my = oracle.hdiff_masks(f.u)
+    shp = (nk, nj + 4, ni + 4)
+    J = _brute_jacobian(lambda e: oracle.hdiff_tangent(e.reshape(shp), mx, my, COEFF), int(np.prod(shp)))
+    lam = inputs.cotangent(ni, nj, nk, child=63)
+    ubar = oracle.hdiff_adjoint(lam, mx, my, COEFF)
+    np.testing.assert_allclose(ubar.ravel(), J.T @ lam.ravel(), rtol=0, atol=1e-14)
+    # the limiter mask matters: the two corners never read are exactly zero
+    for k in range(nk):
+        for (jj, ii) in [(0, 0), (0, 1), (1, 0)]:
+            assert ubar[k, jj, ii] == 0.0
+
+
+def test_tangent_is_derivative_of_forward(oracle):
+    """Masks fixed, the step is affine in u: central differences reproduce
+    the tangent wherever the masks of u +- h v agree with those of u."""
+    ni, nj, nk = 12, 10, 6
+    f = inputs.fields_sized(ni, nj, nk, seed=64)
+    _, mx, my = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    v, _ = inputs.dot_vectors(ni, nj, nk)
+    h = 1e-7
+    up, mxp, myp = oracle.step(f.u + h * v, f.data, f.w, COEFF, DT_DZ)
+    um, mxm, mym = oracle.step(f.u - h * v, f.data, f.w, COEFF, DT_DZ)
+    assert np.array_equal(mxp, mx) and np.array_equal(mxm, mx)
+    assert np.array_equal(myp, my) and np.array_equal(mym, my)
+    fd = (_interior(up) - _interior(um)) / (2 * h)
+    tl = oracle.step_tangent(v, f.w, mx, my, COEFF, DT_DZ)
+    np.testing.assert_allclose(fd, tl, rtol=0, atol=1e-7)
+
+
+def test_p11_dot_test(oracle):
+    ni, nj, nk = 48, 40, 24
+    f = inputs.fields_sized(ni, nj, nk, seed=65)
+    _, mx, my = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    v, wv = inputs.dot_vectors(ni, nj, nk)
+    Jv = oracle.step_tangent(v, f.w, mx, my, COEFF, DT_DZ)
+    JTw, _ = oracle.step_adjoint(wv, f.w, mx, my, COEFF, DT_DZ)
+    lhs = math.fsum((Jv * wv).ravel())
+    rhs = math.fsum((v * JTw).ravel())
+    assert abs(lhs - rhs) / max(abs(lhs), abs(rhs)) <= 1e-10
+
+
+def test_p12_central_finite_differences(oracle):
+    """Central differences of <ob, step(u)> at 64 seeded points, h = 1e-6."""
+    ni, nj, nk = 40, 36, 24
+    f = inputs.fields_sized(ni, nj, nk, seed=66)
+    _, mx, my = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    ob = inputs.cotangent(ni, nj, nk)
+    ubar, _ = oracle.step_adjoint(ob, f.w, mx, my, COEFF, DT_DZ)
+    h = 1e-6
+    checked = 0
+    for p in inputs.fd_points(ni, nj, nk, 64):
+        up = f.u.copy().ravel()
+        um = f.u.copy().ravel()
+        up[p] += h
+        um[p] -= h
+        sp, mxp, myp = oracle.step(up.reshape(f.u.shape), f.data, f.w, COEFF, DT_DZ)
+        sm, mxm, mym = oracle.step(um.reshape(f.u.shape), f.data, f.w, COEFF, DT_DZ)
+        if not (np.array_equal(mxp, mx) and np.array_equal(mxm, mx) and np.array_equal(myp, my)
+                and np.array_equal(mym, my)):
+            continue  # a limiter kink lies within h: the a.e. derivative does not apply
+        fd = (math.fsum((_interior(sp) * ob).ravel()) - math.fsum((_interior(sm) * ob).ravel())) / (2 * h)
+        g = ubar.ravel()[p]
+        assert abs(fd - g) <= 1e-7 * max(1.0, abs(g)), (p, fd, g)
+        checked += 1
+    assert checked >= 56
+
+
+# ---------------------------------------------------------------- semantics
+def test_halo_is_carried_not_computed(oracle):
+    f = inputs.fields_sized(7, 6, 4, seed=70)
+    nxt, _, _ = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    mask = np.ones(f.u.shape, bool)
+    mask[:, 2:-2, 2:-2] = False
+    assert np.array_equal(nxt[mask], f.u[mask])
+
+
+def test_corner_halo_points_never_read(oracle):
+    """Only the radius-2 diamond of each output point is read: the three
+    corner-most halo points of each corner do not influence the step."""
+    f = inputs.fields_sized(7, 6, 3, seed=71)
+    base, _, _ = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    u2 = f.u.copy()
+    for (jj, ii) in [(0, 0), (0, 1), (1, 0), (0, -1), (0, -2), (1, -1), (-1, 0), (-2, 0), (-1, 1),
+                     (-1, -1), (-1, -2), (-2, -1)]:
+        u2[:, jj, ii] = 1e6
+    nxt, _, _ = oracle.step(u2, f.data, f.w, COEFF, DT_DZ)
+    assert np.array_equal(_interior(nxt), _interior(base))
