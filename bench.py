@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused hdiff + vadv time step on one MI355X.
+
+Workload: the fused time step at 512 x 512 x 80 (halo 2), FP64, seeded
+synthetic fields (u ~ U[0,1), w ~ U[-1,1] on 81 levels, data ~ U[-0.1,0.1],
+coeff 0.025, dt/dz 0.5), K steps captured in one hipGraph (ping-pong state,
+frozen halo) and timed with HIP events on the capture/launch stream.
+
+Prints ONE JSON line: grid points/s of the step (value), HBM GB/s and the
+fraction of the 8 TB/s peak (roofline), the adjoint/forward time ratio,
+FP32 and plain-kernel comparisons, and the CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "grid points/s and HBM GB/s (% of peak) for fused hdiff+vadv step; adjoint/fwd ratio"
+KERNEL_SOURCES = ["common.hpp", "k_step.hpp", "k_step.hip", "k_step_inst.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fused_512x512x80_f64.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_08322_amd", "csrc", s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def step_bytes(ni, nj, nk, es, mask=False) -> int:
+    """Algorithmic HBM bytes of one fused step: u with its halo, data, the
+    interior levels 1..nk-1 of w (w_0 and w_nk never enter the matrix), the
+    new interior; plus 2 bits per point when the limiter mask is saved."""
+    b = es * (nk * (ni + 4) * (nj + 4) + nk * ni * nj + (nk - 1) * ni * nj + nk * ni * nj)
+    if mask:
+        b += nk * nj * ((ni + 63) // 64) * 8 * 2 + nk * (ni + nj)
+    return b
+
+
+def adjoint_bytes(ni, nj, nk, es) -> int:
+    """Algorithmic bytes of the step adjoint with data_bar: read x_bar, w
+    (levels 1..nk-1) and the mask, write u_bar (padded) and data_bar."""
+    return es * (nk * ni * nj + (nk - 1) * ni * nj + nk * (ni + 4) * (nj + 4) + nk * ni * nj) + \
+        nk * nj * ((ni + 63) // 64) * 16 + nk * (ni + nj)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only-step", action="store_true", help="time the fused forward step only")
+    ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
+              "part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2311_08322_amd import api, fields, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    wl = inputs.STEP_512
+    ni, nj, nk = wl.ni, wl.nj, wl.nk
+    dims = (ni, nj, nk)
+    npts = ni * nj * nk
+    f = inputs.fields_for(wl)
+    K, W = args.steps, args.warmup
+    out = {}
+
+    def mkfields(dtype):
+        u_a = fields.from_padded(f.u, dtype, dev)
+        u_b = fields.from_padded(f.u, dtype, dev)
+        data = fields.from_interior(f.data, dtype, dev)
+        w = fields.from_interior(f.w, dtype, dev)
+        return u_a, u_b, data, w
+
+    def time_graph(dtype, nsteps, reps):
+        u_a, u_b, data, w = mkfields(dtype)
+        s = torch.cuda.Stream()
+        for n in range(W):  # eager warm-up steps
+            src, dst = (u_a, u_b) if n % 2 == 0 else (u_b, u_a)
+            api.stencil_step(src, data, w, dst, dims, inputs.COEFF, inputs.DT_DZ, stream=s)
+        g = api.stencil_graph_capture_steps(nsteps, u_a, u_b, data, w, dims, inputs.COEFF, inputs.DT_DZ,
+                                            stream=s)
+        try:
+            api.stencil_graph_launch(g, stream=s)  # warm replay
+            s.synchronize()
+            times = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                e0.record(s)
+                api.stencil_graph_launch(g, stream=s)
+                e1.record(s)
+                s.synchronize()
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                times.append((e0.elapsed_time(e1) / 1e3, wall))
+        finally:
+            api.stencil_graph_destroy(g)
+        times.sort()
+        return times[len(times) // 2]
+
+    def time_eager(fn, reps=20):
+        s = torch.cuda.current_stream()
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    # ---------------------------------------------------------------- FP64 step
+    print(f"bench: fused step {dims} fp64, {K} steps per graph, {args.reps} replays", file=sys.stderr,
+          flush=True)
+    t_ev, t_wall = time_graph(torch.float64, K, args.reps)
+    t_step = t_ev / K
+    b64 = step_bytes(ni, nj, nk, 8)
+    gbs = b64 / t_step / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": b64, "kernel": "k_step_fused<double,64,4,80,2,1>",
+            "avg_launch_us": round(t_step * 1e6, 2)}
+    out.update({
+        "metric": METRIC, "value": round(npts * K / t_ev, 1), "unit": "grid points/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded U[0,1) u, U[-1,1] w, U[-0.1,0.1] data)",
+        "config": {"workload": "fused hdiff+vadv step 512x512x80, halo 2, hipGraph of K steps",
+                   "ni": ni, "nj": nj, "nk": nk, "graph_steps": K, "wall_s_per_graph": round(t_wall, 6)},
+        "roofline": roof,
+    })
+
+    if not args.only_step:
+        # ------------------------------------------------------------ FP32 step
+        print("bench: fused step fp32", file=sys.stderr, flush=True)
+        t32, _ = time_graph(torch.float32, K, args.reps)
+        b32 = step_bytes(ni, nj, nk, 4)
+        out["fp32"] = {"value": round(npts * K / t32, 1), "unit": "grid points/s",
+                       "ms_per_step": round(t32 / K * 1e3, 4), "gbs": round(b32 / (t32 / K) / 1e9, 1),
+                       "frac": round(b32 / (t32 / K) / 1e9 / PEAK_GBS, 4)}
+        # ------------------------------------------------ adjoint / forward ratio
+        print("bench: adjoint vs forward (eager, mask saved)", file=sys.stderr, flush=True)
+        u_a, u_b, data, w = mkfields(torch.float64)
+        mask = fields.mask_tensor(dims, dev)
+        xb = fields.from_interior(inputs.cotangent(ni, nj, nk), torch.float64, dev)
+        ub = fields.alloc(ni, nj, nk, torch.float64, dev, fill=0.0)
+        db = fields.alloc(ni, nj, nk, torch.float64, dev, halo=0, fill=0.0)
+        t_fwd = time_eager(lambda: api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ,
+                                                    mask=mask))
+        t_adj = time_eager(lambda: api.stencil_step_adjoint(xb, w, mask, ub, db, dims, inputs.COEFF,
+                                                            inputs.DT_DZ))
+        ab = adjoint_bytes(ni, nj, nk, 8)
+        out["adjoint"] = {"ratio_adj_over_fwd": round(t_adj / t_fwd, 3), "fwd_mask_ms": round(t_fwd * 1e3, 4),
+                          "adj_ms": round(t_adj * 1e3, 4), "adj_gbs": round(ab / t_adj / 1e9, 1),
+                          "adj_frac": round(ab / t_adj / 1e9 / PEAK_GBS, 4),
+                          "fwd_mask_gbs": round(step_bytes(ni, nj, nk, 8, True) / t_fwd / 1e9, 1)}
+        # ------------------------------------------------ plain per-stage chain
+        print("bench: plain per-stage kernels", file=sys.stderr, flush=True)
+        po = api.Options(impl=api.IMPL_PLAIN)
+        po.workspace = fields.workspace(api.OP_STEP, torch.float64, dims, po)
+        t_plain = time_eager(lambda: api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ,
+                                                      opts=po), reps=10)
+        del po
+        out["plain"] = {"ms_per_step": round(t_plain * 1e3, 4), "fused_speedup": round(t_plain / t_step, 3)}
+        # ------------------------------------------------ call vs kernel time
+        s = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        n = 50
+        t0 = time.perf_counter()
+        for _ in range(n):
+            api.stencil_step(u_a, data, w, u_b, (8, 8, 8), inputs.COEFF, inputs.DT_DZ)
+        host_call = (time.perf_counter() - t0) / n
+        torch.cuda.synchronize()
+        out["python_call_us"] = round(host_call * 1e6, 2)
+        del u_a, u_b, data, w, mask, xb, ub, db
+
+    # -------------------------------------------------------------- CPU baseline
+    if not args.no_cpu:
+        from oracle import oracle as orc
+
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        nrep, t0 = 0, time.perf_counter()
+        while nrep < 5 and time.perf_counter() - t0 < 20.0:
+            orc.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ)
+            nrep += 1
+        tc = (time.perf_counter() - t0) / nrep
+        out["cpu_baseline"] = {"value": round(npts / tc, 1), "unit": "grid points/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{nrep} full FP64 steps of the 512x512x80 workload, single-threaded C "
+                                         f"loops (gcc -O2), {tc:.2f} s/step"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,258 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) stencil library (libgt4mi.so).
+ *
+ * What is computed (GT4Py paper, Sec. 3.1: the two benchmark stencils, a
+ * multi-stage horizontal diffusion and an implicit vertical advection):
+ *
+ *   horizontal diffusion (hdiff), per level k, over the interior I:
+ *     lap(i,j) = 4u(i,j) - u(i-1,j) - u(i+1,j) - u(i,j-1) - u(i,j+1)
+ *     fx(i,j)  = lap(i+1,j) - lap(i,j), set to 0 where fx*(u(i+1,j)-u(i,j)) > 0
+ *     fy(i,j)  = lap(i,j+1) - lap(i,j), set to 0 where fy*(u(i,j+1)-u(i,j)) > 0
+ *     out(i,j) = u(i,j) - coeff*(fx(i,j) - fx(i-1,j) + fy(i,j) - fy(i,j-1))
+ *   vertical advection (vadv), per column, r = dt_dz:
+ *     a_k = -r/4 w_k (k >= 1), a_0 = 0;  c_k = r/4 w_{k+1} (k <= nk-2),
+ *     c_{nk-1} = 0;  b_k = 1 + |a_k| + |c_k|;  d_k = u_k + data_k;
+ *     solve a_k x_{k-1} + b_k x_k + c_k x_{k+1} = d_k (Thomas algorithm:
+ *     FORWARD elimination then BACKWARD substitution, Sec. 2.2).
+ *   step: hdiff, then vadv with the diffused field as u_k.
+ *   adjoints: transposes of the a.e. Jacobians with the limiter decisions of
+ *     the forward pass held fixed (the mask), used by reverse-mode AD.
+ *
+ * A call follows the paper's statement of a stencil call (Sec. 2.2): fields,
+ * read-only scalar parameters, and an iteration space given by a domain and
+ * per-field origins; the vertical interval of a call is [0, nk) relative to
+ * each field's origin; the horizontal halo is 2 (the stencil's radius).
+ *
+ * Conventions
+ *   - All pointers in stencil_field.data, masks and workspaces are DEVICE
+ *     pointers (hipMalloc'd or torch CUDA tensors).  Struct arguments
+ *     themselves are host memory, read during the call only.
+ *   - The caller owns every buffer.  The library never frees caller memory
+ *     and never synchronises the device.  All compute calls are
+ *     asynchronous on `stream` (NULL = the legacy default stream).
+ *   - Errors: every int-returning call returns STENCIL_OK (0) or a negative
+ *     STENCIL_E_* code; a message is kept in thread-local storage, read by
+ *     stencil_last_error().  No exception crosses the ABI and nothing aborts.
+ *     Argument validation reads host metadata only (O(1), no device access).
+ *     Asynchronous kernel faults surface on a later call as STENCIL_E_HIP.
+ *   - Outputs must not overlap inputs (an assignment is evaluated over the
+ *     whole domain before it is stored, Sec. 2.2): STENCIL_E_ALIAS.
+ */
+#ifndef GT4MI_STENCIL_H
+#define GT4MI_STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STENCIL_ABI_VERSION 1
+#define STENCIL_HALO 2
+
+typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype;
+
+enum {
+  STENCIL_OK = 0,
+  STENCIL_E_NULL = -1,        /* a required pointer is NULL */
+  STENCIL_E_DTYPE = -2,       /* unknown dtype, or misaligned data pointer */
+  STENCIL_E_SHAPE = -3,       /* domain/origin/shape inconsistent */
+  STENCIL_E_HALO = -4,        /* a field lacks the 2-point halo it needs */
+  STENCIL_E_STRIDE = -5,      /* stride[0] != 1 or overlapping strides */
+  STENCIL_E_ALIAS = -6,       /* an output overlaps an input */
+  STENCIL_E_WORKSPACE = -7,   /* workspace missing or too small */
+  STENCIL_E_UNSUPPORTED = -8, /* e.g. nk beyond the largest compiled class */
+  STENCIL_E_HIP = -9,         /* a HIP runtime error (message attached) */
+  STENCIL_E_ARG = -10         /* any other invalid argument */
+};
+
+/* A 3D field in device memory, index order (i, j, k), i fastest.
+ *   data   : device pointer to allocation element (0,0,0)
+ *   shape  : allocation extents in elements (i, j, k)
+ *   stride : element strides; stride[0] must be 1; rows and planes must not
+ *            overlap (stride[1] >= shape[0], stride[2] >= stride[1]*shape[1])
+ *   origin : allocation index of compute-domain point (0,0,0)
+ * Element (i,j,k) of the compute domain lives at
+ *   data + (origin[0]+i) + (origin[1]+j)*stride[1] + (origin[2]+k)*stride[2].
+ * Fields read with a halo need origin[0..1] >= 2 and
+ * origin[d] + domain[d] + 2 <= shape[d] for d = 0, 1. */
+typedef struct {
+  void* data;
+  int64_t shape[3];
+  int64_t stride[3];
+  int64_t origin[3];
+} stencil_field;
+
+typedef enum {
+  STENCIL_IMPL_AUTO = 0,  /* fused kernels, tile from the tuning table */
+  STENCIL_IMPL_FUSED = 1, /* all stages in one kernel, temporaries on chip */
+  STENCIL_IMPL_PLAIN = 2  /* one kernel per stage, temporaries in HBM */
+} stencil_impl;
+
+typedef enum {
+  STENCIL_COLUMN_AUTO = 0,
+  STENCIL_COLUMN_REGISTERS = 1, /* elimination factors of a column in VGPRs */
+  STENCIL_COLUMN_OUTBUF = 2     /* c' in VGPRs, d' staged in the output field */
+} stencil_column_store;
+
+/* Optional per-call options; pass NULL for defaults. */
+typedef struct {
+  int32_t impl;         /* stencil_impl */
+  int32_t tile_i;       /* horizontal tile of the fused kernels; 0 = tuned */
+  int32_t tile_j;       /*   supported: 64x4, 32x8, 16x16 */
+  int32_t column_store; /* stencil_column_store */
+  void* workspace;      /* device memory for STENCIL_IMPL_PLAIN temporaries */
+  size_t workspace_bytes;
+} stencil_options;
+
+typedef enum {
+  STENCIL_OP_HDIFF = 0,
+  STENCIL_OP_VADV = 1,
+  STENCIL_OP_STEP = 2,
+  STENCIL_OP_HDIFF_ADJOINT = 3,
+  STENCIL_OP_VADV_ADJOINT = 4,
+  STENCIL_OP_STEP_ADJOINT = 5
+} stencil_op;
+
+/* ---------------------------------------------------------------- info */
+/* ABI version (STENCIL_ABI_VERSION). */
+int stencil_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char* stencil_last_error(void);
+/* Largest nk the fused column kernels accept (longer columns: PLAIN). */
+int stencil_max_fused_nk(stencil_dtype dtype);
+
+/* Bytes of the limiter mask of a domain (device buffer, caller-owned).
+ * Layout, for W = ceil(ni/64) 64-bit words per row, all sections 256-byte
+ * aligned, bit b of a word = i = 64*word + b, 1 = flux kept:
+ *   X plane  uint64[nk][nj][W] : flux between (i,j) and (i+1,j), i in [0,ni)
+ *   Y plane  uint64[nk][nj][W] : flux between (i,j) and (i,j+1), i in [0,ni)
+ *   X edge   uint8 [nk][nj]    : flux between (-1,j) and (0,j)
+ *   Y edge   uint8 [nk][ni]    : flux between (i,-1) and (i,0)
+ * Returns 0 for an invalid domain. */
+size_t stencil_mask_bytes(const int64_t domain[3]);
+
+/* Device workspace needed by `op` under `opts` (0 if none).  PLAIN forms
+ * keep their stage temporaries there; STEP_ADJOINT without a data_bar
+ * output keeps the column adjoint there. */
+size_t stencil_workspace_bytes(int op, stencil_dtype dtype, const int64_t domain[3],
+                               const stencil_options* opts);
+
+/* ------------------------------------------------------------- forward */
+/* Horizontal diffusion (Sec. 3.1).  u: read on the domain plus a 2-point
+ * halo in i and j.  out: the interior is written, its halo is untouched.
+ * mask: NULL, or stencil_mask_bytes(domain) device bytes that receive the
+ * limiter decisions. */
+int stencil_hdiff(stencil_dtype dtype, const stencil_field* u, stencil_field* out,
+                  const int64_t domain[3], double coeff, void* mask,
+                  const stencil_options* opts, hipStream_t stream);
+
+/* Vertical advection (Sec. 3.1): out = T(w)^{-1} (u + data) per column.
+ * u, data: domain; w: nk+1 staggered levels (w_0 and w_nk are not read);
+ * out: domain (interior only). */
+int stencil_vadv(stencil_dtype dtype, const stencil_field* u, const stencil_field* data,
+                 const stencil_field* w, stencil_field* out, const int64_t domain[3],
+                 double dt_dz, const stencil_options* opts, hipStream_t stream);
+
+/* One time step: out = vadv(hdiff(u), data, w).  Arguments as above; the
+ * halo of out is untouched, so ping-pong buffers with equal halos keep a
+ * frozen boundary. */
+int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_field* data,
+                 const stencil_field* w, stencil_field* out, const int64_t domain[3],
+                 double coeff, double dt_dz, void* mask, const stencil_options* opts,
+                 hipStream_t stream);
+
+/* ------------------------------------------------------------- adjoint */
+/* u_bar = J_hdiff^T out_bar with the forward limiter mask held fixed.
+ * out_bar: domain.  u_bar: written over the domain plus its 2-point halo
+ * (every padded point is overwritten, the corner points never read by the
+ * forward stencil receive 0).  mask: from a forward call on this domain. */
+int stencil_hdiff_adjoint(stencil_dtype dtype, const stencil_field* out_bar, const void* mask,
+                          stencil_field* u_bar, const int64_t domain[3], double coeff,
+                          const stencil_options* opts, hipStream_t stream);
+
+/* d_bar = T(w)^{-T} x_bar per column, coefficients recomputed from w. */
+int stencil_vadv_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
+                         const stencil_field* w, stencil_field* d_bar,
+                         const int64_t domain[3], double dt_dz, const stencil_options* opts,
+                         hipStream_t stream);
+
+/* Adjoint of stencil_step: lambda = T^{-T} x_bar; u_bar = J_hdiff^T lambda
+ * (domain plus halo); data_bar = lambda if data_bar is not NULL (else the
+ * workspace of opts holds lambda, stencil_workspace_bytes(STEP_ADJOINT)). */
+int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
+                         const stencil_field* w, const void* mask, stencil_field* u_bar,
+                         stencil_field* data_bar, const int64_t domain[3], double coeff,
+                         double dt_dz, const stencil_options* opts, hipStream_t stream);
+
+/* ------------------------------------------------------------- batched */
+/* One field of a batch: forward step out = step(u, data, w) on `domain`. */
+typedef struct {
+  stencil_field u, data, w, out;
+  int64_t domain[3];
+  double coeff, dt_dz;
+  void* mask; /* NULL or stencil_mask_bytes(domain) bytes */
+} stencil_batch_item;
+
+/* One field of an adjoint batch. */
+typedef struct {
+  stencil_field x_bar, w, u_bar, data_bar; /* data_bar.data may be NULL */
+  int64_t domain[3];
+  double coeff, dt_dz;
+  const void* mask;
+} stencil_batch_adjoint_item;
+
+/* Workspace for a batch: the work list and queue counter (and, for the
+ * adjoint, the column adjoints of items without data_bar). */
+size_t stencil_batch_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_item* items);
+size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
+                                             const stencil_batch_adjoint_item* items);
+
+/* All n steps in one persistent launch: workgroups pull (field, tile) work
+ * items, longest first, from a device queue in `ws`. */
+int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
+                         size_t ws_bytes, const stencil_options* opts, hipStream_t stream);
+/* The adjoints of a batch: one persistent launch for the column adjoints,
+ * one for the horizontal gathers. */
+int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
+                                 const stencil_batch_adjoint_item* items, void* ws,
+                                 size_t ws_bytes, const stencil_options* opts,
+                                 hipStream_t stream);
+
+/* ---------------------------------------------------------- hipGraph loop */
+typedef struct stencil_graph stencil_graph;
+
+/* Captures nsteps stencil_step calls into a HIP graph: step s reads the
+ * buffer it did not write at step s-1 (u_a -> u_b -> u_a ...), so after the
+ * graph runs the state is in u_b for odd nsteps and in u_a for even.  Both
+ * buffers must hold the same halo.  `stream` is used for capture only. */
+int stencil_graph_capture_steps(stencil_dtype dtype, int nsteps, stencil_field* u_a,
+                                stencil_field* u_b, const stencil_field* data,
+                                const stencil_field* w, const int64_t domain[3], double coeff,
+                                double dt_dz, const stencil_options* opts, hipStream_t stream,
+                                stencil_graph** graph);
+int stencil_graph_launch(stencil_graph* graph, hipStream_t stream);
+int stencil_graph_destroy(stencil_graph* graph);
+
+/* ---------------------------------------------------------------- tuning */
+/* Times every tile candidate of `op` on a domain of this size (scratch
+ * fields allocated and freed by the library for the duration of the call,
+ * device synchronised) and records the fastest in the process-wide tuning
+ * table under (dtype, op, size class).  *best_us receives its time. */
+int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int reps,
+                     double* best_us);
+/* Tile chosen for (dtype, op, domain) -- tuned entry or the default. */
+int stencil_tuning_lookup(stencil_dtype dtype, int op, const int64_t domain[3], int32_t* tile_i,
+                          int32_t* tile_j, int32_t* column_store);
+/* Persist / restore the tuning table as JSON. */
+int stencil_save_tuning(const char* json_path);
+int stencil_load_tuning(const char* json_path);
+int stencil_clear_tuning(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GT4MI_STENCIL_H */

@@ -1,0 +1,99 @@
+// common.hpp -- device-side views, kernel argument blocks and small helpers
+// shared by the gfx950 kernels of the stencil library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt4mi {
+
+constexpr int kHalo = 2;
+constexpr int kNumXcd = 8;        // MI355X: 8 XCDs, workgroups dispatched round-robin
+constexpr int kWG = 256;          // threads per workgroup of every tile kernel
+
+// ------------------------------------------------------------------ mask
+// Packed limiter decisions of one domain (1 = flux kept), see stencil.h.
+struct MaskLayout {
+  int64_t words;  // 64-bit words per row: ceil(ni / 64)
+  int64_t x_off, y_off, ex_off, ey_off, total;
+
+  __host__ __device__ static int64_t round256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+  __host__ __device__ static MaskLayout make(int64_t ni, int64_t nj, int64_t nk) {
+    MaskLayout m;
+    if (ni <= 0 || nj <= 0 || nk <= 0) {  // an empty domain has no fluxes
+      m.words = m.x_off = m.y_off = m.ex_off = m.ey_off = m.total = 0;
+      return m;
+    }
+    m.words = (ni + 63) / 64;
+    const int64_t plane = round256(8 * m.words * nj * nk);
+    m.x_off = 0;
+    m.y_off = plane;
+    m.ex_off = 2 * plane;
+    m.ey_off = m.ex_off + round256(nj * nk);
+    m.total = m.ey_off + round256(ni * nk);
+    return m;
+  }
+};
+
+// ------------------------------------------------------------ XCD mapping
+// The dispatcher hands workgroup b to XCD (b % 8).  Give each XCD one
+// contiguous run of tiles so that tiles sharing halo rows share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int q = nblocks / kNumXcd, r = nblocks % kNumXcd;
+  const int x = b % kNumXcd, local = b / kNumXcd;
+  return x * q + (x < r ? x : r) + local;
+}
+
+// ------------------------------------------------------------ limiter
+// The flux is zeroed where flux * gradient > 0 (Sec. 3.1 benchmark
+// definition), taken as a sign test so that underflow of the product
+// cannot flip it.
+template <typename T>
+__device__ __forceinline__ bool flux_kept(T f, T g) {
+  const bool zeroed = (f > T(0) && g > T(0)) || (f < T(0) && g < T(0));
+  return !zeroed;
+}
+
+template <typename T>
+__device__ __forceinline__ T recip(T m) {
+  return T(1) / m;
+}
+
+// ------------------------------------------------------------ argument blocks
+template <typename T>
+struct StepArgs {
+  const T* u;  // at domain point (0,0,0); read with a 2-point halo
+  int64_t u_sj, u_sk;
+  const T* data;
+  int64_t d_sj, d_sk;
+  const T* w;  // staggered level 0
+  int64_t w_sj, w_sk;
+  T* out;
+  int64_t o_sj, o_sk;
+  uint8_t* mask;  // nullable
+  MaskLayout ml;
+  int ni, nj, nk;
+  int tiles_i, ntiles;
+  int k0, k1;  // level range of this launch (hdiff kernels)
+  T coeff, r4;  // r4 = dt_dz / 4
+};
+
+template <typename T>
+struct AdjArgs {
+  const T* xbar;  // domain
+  int64_t x_sj, x_sk;
+  const T* w;
+  int64_t w_sj, w_sk;
+  T* lam;  // domain (column adjoint output, data_bar)
+  int64_t l_sj, l_sk;
+  T* ubar;  // at domain (0,0,0); written over the 2-point halo too
+  int64_t b_sj, b_sk;
+  const uint8_t* mask;
+  MaskLayout ml;
+  int ni, nj, nk;
+  int tiles_i, ntiles;
+  T coeff, r4;
+};
+
+}  // namespace gt4mi

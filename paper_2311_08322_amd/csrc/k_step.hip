@@ -1,0 +1,47 @@
+// k_step.hip -- host dispatch of the fused forward column kernels (the
+// register classes themselves are instantiated in k_step_inst.hip).
+#include "launch.hpp"
+
+namespace gt4mi {
+
+template <typename T, int COL>
+static hipError_t step_by_tile(const StepArgs<T>& A, int tile_i, hipStream_t s) {
+  if (tile_i == 64) return launch_step_classes<T, 64, 4, COL>(A, s);
+  if (tile_i == 32) return launch_step_classes<T, 32, 8, COL>(A, s);
+  return launch_step_classes<T, 16, 16, COL>(A, s);
+}
+
+template <typename T>
+hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) {
+  const int tj = kWG / tile_i;
+  A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+  A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
+  if constexpr (sizeof(T) == 4) {
+    // binary32 columns up to the largest class fit their registers
+    (void)col;
+    return step_by_tile<T, 1>(A, tile_i, s);
+  } else {
+    // FP64 beyond 96 levels stages d' in the output field
+    if (col == 2 || A.nk > 96) return step_by_tile<T, 2>(A, tile_i, s);
+    return step_by_tile<T, 1>(A, tile_i, s);
+  }
+}
+
+template <typename T>
+hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s) {
+  A.tiles_i = (A.ni + 63) / 64;
+  A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
+  if constexpr (sizeof(T) == 4) {
+    return launch_vadv_classes<T, 1>(A, s);
+  } else {
+    if (A.nk > 96) return launch_vadv_classes<T, 2>(A, s);
+    return launch_vadv_classes<T, 1>(A, s);
+  }
+}
+
+template hipError_t launch_step_fused<float>(StepArgs<float>, int, int, hipStream_t);
+template hipError_t launch_step_fused<double>(StepArgs<double>, int, int, hipStream_t);
+template hipError_t launch_vadv_fused<float>(StepArgs<float>, hipStream_t);
+template hipError_t launch_vadv_fused<double>(StepArgs<double>, hipStream_t);
+
+}  // namespace gt4mi

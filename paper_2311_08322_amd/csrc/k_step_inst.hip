@@ -1,0 +1,17 @@
+// k_step_inst.hip -- explicit instantiations of the fused column kernels,
+// one (dtype, tile, column store) set per compilation of this file:
+//   -DGT4MI_T=double|float -DGT4MI_TI=64|32|16 -DGT4MI_COL=1|2  (step)
+//   -DGT4MI_T=... -DGT4MI_VADV -DGT4MI_COL=1|2                   (vadv)
+// Splitting keeps each fully unrolled register class in a parallel job.
+#include "k_step.hpp"
+
+namespace gt4mi {
+
+#if defined(GT4MI_VADV)
+template hipError_t launch_vadv_classes<GT4MI_T, GT4MI_COL>(const StepArgs<GT4MI_T>&, hipStream_t);
+#else
+template hipError_t launch_step_classes<GT4MI_T, GT4MI_TI, 256 / GT4MI_TI, GT4MI_COL>(
+    const StepArgs<GT4MI_T>&, hipStream_t);
+#endif
+
+}  // namespace gt4mi

@@ -1,0 +1,270 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every declared entry point, and argument validation rejects bad
+calls with the documented status codes before any device work.  Field data
+pointers here are fake (never dereferenced: validation reads metadata only).
+"""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2311_08322_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in stencil.h but not exported"
+    # and the binding covers the same names
+    from paper_2311_08322_amd import api
+
+    for n in names:
+        assert hasattr(api, n), f"python binding lacks {n}"
+
+
+def test_version_and_limits(L):
+    assert L.stencil_version() == 1
+    assert L.stencil_max_fused_nk(1) >= 137
+
+
+def test_mask_bytes(L):
+    # 64x64x16: one word per row; X and Y planes 8*64*16 B; edges 64*16 B each
+    assert L.stencil_mask_bytes(_lib.domain3((64, 64, 16))) == 8192 * 2 + 1024 * 2
+    # 65 columns need two words per row
+    d = (65, 3, 2)
+    plane = (8 * 2 * 3 * 2 + 255) // 256 * 256
+    assert L.stencil_mask_bytes(_lib.domain3(d)) == 2 * plane + 256 + 256
+    assert L.stencil_mask_bytes(_lib.domain3((-1, 3, 2))) == 0
+    assert L.stencil_mask_bytes(None) == 0
+    assert L.stencil_mask_bytes(_lib.domain3((0, 5, 5))) == 0
+
+
+def test_workspace_bytes(L):
+    d = _lib.domain3((64, 48, 16))
+    assert L.stencil_workspace_bytes(_lib.OP_STEP, _lib.F64, d, None) == 0
+    o = _lib.StencilOptions()
+    o.impl = _lib.IMPL_PLAIN
+    plain = L.stencil_workspace_bytes(_lib.OP_STEP, _lib.F64, d, ctypes.byref(o))
+    # lap, fx, fy and the two elimination arrays: about 5 fields
+    n = 64 * 48 * 16 * 8
+    assert 5 * n <= plain <= 5 * n + 5 * 256 + 8 * (66 * 50 - 64 * 48) * 16 + 8 * (65 + 49) * 16
+    assert L.stencil_workspace_bytes(_lib.OP_STEP, _lib.F32, d, ctypes.byref(o)) < plain
+    # the step adjoint keeps lambda in the workspace when data_bar is absent
+    assert L.stencil_workspace_bytes(_lib.OP_STEP_ADJOINT, _lib.F64, d, None) >= n
+    # columns longer than the fused classes need the plain workspace
+    long = _lib.domain3((8, 8, 200))
+    assert L.stencil_workspace_bytes(_lib.OP_STEP, _lib.F64, long, None) > 0
+
+
+# ----------------------------------------------------------------- validation
+BASE = 0x7F0000000000
+
+
+def fld(ni, nj, nk, halo=2, kextra=0, base=BASE, es=8):
+    f = _lib.StencilField()
+    f.data = base
+    Ni, Nj = ni + 2 * halo, nj + 2 * halo
+    f.shape = _lib.I64x3(Ni, Nj, nk + kextra)
+    f.stride = _lib.I64x3(1, Ni, Ni * Nj)
+    f.origin = _lib.I64x3(halo, halo, 0)
+    return f
+
+
+def fields(ni=16, nj=12, nk=8):
+    span = (ni + 4) * (nj + 4) * (nk + 1) * 8 + 4096
+    u = fld(ni, nj, nk, base=BASE)
+    data = fld(ni, nj, nk, halo=0, base=BASE + span)
+    w = fld(ni, nj, nk, halo=0, kextra=1, base=BASE + 2 * span)
+    out = fld(ni, nj, nk, base=BASE + 3 * span)
+    return u, data, w, out, _lib.domain3((ni, nj, nk))
+
+
+def step(L, u, data, w, out, d, mask=None, opts=None, dt=_lib.F64):
+    b = ctypes.byref
+    return L.stencil_step(dt, b(u) if u else None, b(data), b(w), b(out), d, 0.025, 0.5, mask,
+                          b(opts) if opts else None, None)
+
+
+def code(name):
+    return _lib.CODES[name]
+
+
+def test_null_and_dtype(L):
+    u, data, w, out, d = fields()
+    assert step(L, None, data, w, out, d) == code("STENCIL_E_NULL")
+    assert "u" in _lib.last_error()
+    assert step(L, u, data, w, out, d, dt=7) == code("STENCIL_E_DTYPE")
+    u.data = None
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_NULL")
+    u, data, w, out, d = fields()
+    u.data = BASE + 4  # not 8-byte aligned for FP64
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_DTYPE")
+
+
+def test_halo_and_shape(L):
+    u, data, w, out, d = fields()
+    u.origin = _lib.I64x3(1, 2, 0)
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_HALO")
+    u, data, w, out, d = fields()
+    u.shape = _lib.I64x3(u.shape[0] - 1, u.shape[1], u.shape[2])
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_HALO")
+    u, data, w, out, d = fields()
+    w.shape = _lib.I64x3(w.shape[0], w.shape[1], w.shape[2] - 1)  # nk levels, needs nk+1
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_SHAPE")
+    assert "w" in _lib.last_error()
+    u, data, w, out, d = fields()
+    d2 = _lib.domain3((16, 13, 8))
+    assert step(L, u, data, w, out, d2) in (code("STENCIL_E_HALO"), code("STENCIL_E_SHAPE"))
+    assert step(L, u, data, w, out, _lib.domain3((16, -1, 8))) == code("STENCIL_E_SHAPE")
+
+
+def test_strides(L):
+    u, data, w, out, d = fields()
+    u.stride = _lib.I64x3(2, u.stride[1], u.stride[2])
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_STRIDE")
+    u, data, w, out, d = fields()
+    u.stride = _lib.I64x3(1, u.shape[0] - 1, u.stride[2])
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_STRIDE")
+
+
+def test_alias(L):
+    u, data, w, out, d = fields()
+    out.data = u.data  # in-place is forbidden (whole-domain assignment semantics)
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_ALIAS")
+    u, data, w, out, d = fields()
+    out.data = data.data + 8 * 5
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_ALIAS")
+    u, data, w, out, d = fields()
+    mask = out.data + 8  # mask overlapping the output
+    assert step(L, u, data, w, out, d, mask=mask) == code("STENCIL_E_ALIAS")
+
+
+def test_options(L):
+    u, data, w, out, d = fields()
+    o = _lib.StencilOptions()
+    o.impl = 9
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    o = _lib.StencilOptions()
+    o.tile_i, o.tile_j = 48, 4
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    o = _lib.StencilOptions()
+    o.impl = _lib.IMPL_PLAIN  # no workspace
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_WORKSPACE")
+    o.workspace = 0x7E0000000000
+    o.workspace_bytes = 64
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_WORKSPACE")
+    assert "smaller" in _lib.last_error()
+
+
+def test_long_columns_need_plain(L):
+    u, data, w, out, d = fields(8, 8, 200)
+    o = _lib.StencilOptions()
+    o.impl = _lib.IMPL_FUSED
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_UNSUPPORTED")
+    # AUTO falls back to PLAIN, which then wants its workspace
+    assert step(L, u, data, w, out, d) == code("STENCIL_E_WORKSPACE")
+
+
+def test_empty_domain_is_a_noop(L):
+    u, data, w, out, d = fields(16, 12, 8)
+    assert step(L, u, data, w, out, _lib.domain3((0, 12, 8))) == 0
+    assert step(L, u, data, w, out, _lib.domain3((16, 12, 0))) == 0
+
+
+def test_adjoint_validation(L):
+    b = ctypes.byref
+    u, data, w, out, d = fields()
+    xb = fld(16, 12, 8, halo=0, base=BASE + (1 << 30))
+    ub = fld(16, 12, 8, base=BASE + (2 << 30))
+    # u_bar needs the halo (it is written there)
+    ub2 = fld(16, 12, 8, halo=0, base=BASE + (2 << 30))
+    assert L.stencil_step_adjoint(1, b(xb), b(w), BASE + (3 << 30), b(ub2), None, d, 0.025, 0.5, None,
+                                  None) == code("STENCIL_E_HALO")
+    # missing mask
+    assert L.stencil_step_adjoint(1, b(xb), b(w), None, b(ub), b(data), d, 0.025, 0.5, None,
+                                  None) == code("STENCIL_E_NULL")
+    # data_bar aliasing x_bar
+    assert L.stencil_step_adjoint(1, b(xb), b(w), BASE + (3 << 30), b(ub), b(xb), d, 0.025, 0.5, None,
+                                  None) == code("STENCIL_E_ALIAS")
+    # no data_bar and no workspace for lambda
+    assert L.stencil_step_adjoint(1, b(xb), b(w), BASE + (3 << 30), b(ub), None, d, 0.025, 0.5, None,
+                                  None) == code("STENCIL_E_WORKSPACE")
+    assert L.stencil_hdiff_adjoint(1, b(xb), None, b(ub), d, 0.025, None, None) == code("STENCIL_E_NULL")
+    assert L.stencil_vadv_adjoint(1, b(xb), b(w), b(xb), d, 0.5, None, None) == code("STENCIL_E_ALIAS")
+
+
+def test_graph_capture_validation(L):
+    b = ctypes.byref
+    u, data, w, out, d = fields()
+    h = ctypes.c_void_p()
+    assert L.stencil_graph_capture_steps(1, 0, b(u), b(out), b(data), b(w), d, 0.025, 0.5, None,
+                                         0x1234, b(h)) == code("STENCIL_E_ARG")
+    assert L.stencil_graph_capture_steps(1, 4, b(u), b(out), b(data), b(w), d, 0.025, 0.5, None,
+                                         None, b(h)) == code("STENCIL_E_ARG")
+    assert L.stencil_graph_capture_steps(1, 4, b(u), b(u), b(data), b(w), d, 0.025, 0.5, None,
+                                         0x1234, b(h)) == code("STENCIL_E_ALIAS")
+    assert L.stencil_graph_launch(None, None) == code("STENCIL_E_NULL")
+    assert L.stencil_graph_destroy(None) == 0
+
+
+# ----------------------------------------------------------------- tuning table
+def test_tuning_json_roundtrip(L, tmp_path):
+    assert L.stencil_clear_tuning() == 0
+    d = _lib.domain3((256, 256, 80))
+    ti, tj, col = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
+    assert (ti.value, tj.value) == (64, 4)
+    p = tmp_path / "tune.json"
+    doc = {"arch": "gfx950", "version": 1, "entries": [
+        {"dtype": 1, "op": _lib.OP_STEP, "nk_class": 5, "area_class": 2, "tile_i": 32, "tile_j": 8,
+         "column_store": 2, "us": 12.5}]}
+    p.write_text(json.dumps(doc))
+    assert L.stencil_load_tuning(str(p).encode()) == 0
+    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
+    assert (ti.value, tj.value, col.value) == (32, 8, 2)
+    # another size class is untouched
+    d2 = _lib.domain3((64, 64, 16))
+    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d2, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
+    assert ti.value == 64
+    q = tmp_path / "saved.json"
+    assert L.stencil_save_tuning(str(q).encode()) == 0
+    saved = json.loads(q.read_text())
+    assert saved["arch"] == "gfx950" and len(saved["entries"]) == 1
+    assert saved["entries"][0]["tile_i"] == 32
+    assert L.stencil_clear_tuning() == 0
+    assert L.stencil_load_tuning(str(q).encode()) == 0
+    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
+    assert ti.value == 32
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"arch": "gfx950", "entries": [{"dtype": 1, "op": 2, "tile_i": 48}]}')
+    assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
+    assert L.stencil_load_tuning(b"/nonexistent/x.json") == code("STENCIL_E_ARG")
+    assert L.stencil_clear_tuning() == 0
+
+
+def test_binding_refuses_unknown_dtype():
+    import torch
+
+    from paper_2311_08322_amd import api
+
+    t = torch.zeros((2, 8, 8), dtype=torch.int32)
+    with pytest.raises(api.StencilError):
+        api.stencil_hdiff(api.Field(t, (2, 2, 0)), api.Field(t.clone(), (2, 2, 0)), (4, 4, 2), 0.025,
+                          stream=0)

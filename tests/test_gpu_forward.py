@@ -1,0 +1,196 @@
+"""GPU parity of the forward stencils against the CPU oracle.
+
+Element-by-element on the same seeded inputs; masks bit-exact; values
+within 1e-12 (FP64) or 2e-5 (FP32, against the FP64 oracle run on the
+binary32-rounded inputs with its limiter decisions taken in binary32)
+relative in the infinity norm.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as orc
+from paper_2311_08322_amd import api, fields, inputs
+
+from .helpers import TOL, c_scalar, dev_fields, host, rel_err, round_f32, unpack_mask
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+DTYPES = [torch.float64, torch.float32]
+
+
+def _ref_inputs(f, dtype):
+    if dtype == torch.float32:
+        return inputs.Fields(u=round_f32(f.u), w=round_f32(f.w), data=round_f32(f.data))
+    return f
+
+
+def _opts(impl, tile=0, col=0, dtype=torch.float64, dom=None, op=api.OP_STEP):
+    o = api.Options(impl=impl, tile_i=tile, tile_j=(256 // tile if tile else 0), column_store=col)
+    if impl == api.IMPL_PLAIN or (dom is not None and dom[2] > api.stencil_max_fused_nk()):
+        o.workspace = fields.workspace(op, dtype, dom, o)
+    return o
+
+
+# ------------------------------------------------------------------ hdiff
+HDIFF_CASES = [(64, 64, 16), (67, 45, 7), (1, 1, 1), (130, 3, 5), (5, 130, 3), (2, 2, 2)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("impl,tile", [(api.IMPL_PLAIN, 0), (api.IMPL_FUSED, 64), (api.IMPL_FUSED, 32),
+                                       (api.IMPL_FUSED, 16)], ids=["plain", "t64", "t32", "t16"])
+@pytest.mark.parametrize("dims", HDIFF_CASES, ids=lambda d: "x".join(map(str, d)))
+def test_hdiff(dims, impl, tile, dtype):
+    ni, nj, nk = dims
+    print(f"hdiff {dims} impl={impl} tile={tile} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=101)
+    r = _ref_inputs(f, dtype)
+    u = fields.from_padded(f.u, dtype, DEV)
+    out = fields.alloc(ni, nj, nk, dtype, DEV, fill=-7.0)
+    mask = fields.mask_tensor(dims, DEV)
+    coeff = c_scalar(inputs.COEFF, dtype)
+    api.stencil_hdiff(u, out, dims, inputs.COEFF, mask=mask, opts=_opts(impl, tile, 0, dtype, dims, api.OP_HDIFF))
+    torch.cuda.synchronize()
+    ref, mx, my = orc.hdiff(r.u, coeff, decide_f32=(dtype == torch.float32))
+    got = host(fields.interior(out, ni, nj, nk))
+    assert rel_err(got, ref[:, 2:-2, 2:-2]) <= TOL[dtype]
+    gmx, gmy = unpack_mask(mask, ni, nj, nk)
+    assert np.array_equal(gmx, mx) and np.array_equal(gmy, my)
+    # the halo of out is untouched
+    full = host(fields.padded(out, ni, nj, nk))
+    ring = np.ones(full.shape, bool)
+    ring[:, 2:-2, 2:-2] = False
+    assert np.all(full[ring] == -7.0)
+
+
+def test_hdiff_config1_without_mask():
+    ni, nj, nk = inputs.HDIFF_64.ni, inputs.HDIFF_64.nj, inputs.HDIFF_64.nk
+    f = inputs.fields_for(inputs.HDIFF_64)
+    u = fields.from_padded(f.u, torch.float64, DEV)
+    out = fields.alloc(ni, nj, nk, torch.float64, DEV, fill=0.0)
+    api.stencil_hdiff(u, out, (ni, nj, nk), inputs.COEFF)
+    ref, _, _ = orc.hdiff(f.u, inputs.COEFF)
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= 1e-12
+
+
+# ------------------------------------------------------------------ vadv
+VADV_NK = [1, 2, 16, 17, 80, 96, 97, 128, 137, 160, 161, 200]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("impl", [api.IMPL_AUTO, api.IMPL_PLAIN], ids=["auto", "plain"])
+@pytest.mark.parametrize("nk", VADV_NK)
+def test_vadv(nk, impl, dtype):
+    ni, nj = 70, 9
+    print(f"vadv nk={nk} impl={impl} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=102)
+    r = _ref_inputs(f, dtype)
+    uin = fields.from_interior(f.u[:, 2:-2, 2:-2], dtype, DEV)
+    data = fields.from_interior(f.data, dtype, DEV)
+    w = fields.from_interior(f.w, dtype, DEV)
+    out = fields.alloc(ni, nj, nk, dtype, DEV, halo=0, fill=0.0)
+    dom = (ni, nj, nk)
+    api.stencil_vadv(uin, data, w, out, dom, inputs.DT_DZ, opts=_opts(impl, 0, 0, dtype, dom, api.OP_VADV))
+    torch.cuda.synchronize()
+    ref = orc.vadv(r.u[:, 2:-2, 2:-2], r.data, r.w, inputs.DT_DZ)
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), ref) <= TOL[dtype]
+
+
+def test_vadv_full_size_residual():
+    """256x256x80 FP64: oracle parity and the GPU solution's own residual."""
+    wl = inputs.STEP_256
+    ni, nj, nk = wl.ni, wl.nj, wl.nk
+    f = inputs.fields_for(wl)
+    uin = fields.from_interior(f.u[:, 2:-2, 2:-2], torch.float64, DEV)
+    data = fields.from_interior(f.data, torch.float64, DEV)
+    w = fields.from_interior(f.w, torch.float64, DEV)
+    out = fields.alloc(ni, nj, nk, torch.float64, DEV, halo=0, fill=0.0)
+    api.stencil_vadv(uin, data, w, out, (ni, nj, nk), inputs.DT_DZ)
+    x = host(fields.interior(out, ni, nj, nk))
+    ref = orc.vadv(f.u[:, 2:-2, 2:-2], f.data, f.w, inputs.DT_DZ)
+    assert rel_err(x, ref) <= 1e-12
+    res = orc.tridiag_apply(x, f.w, inputs.DT_DZ) - (f.u[:, 2:-2, 2:-2] + f.data)
+    assert np.max(np.abs(res)) < 1e-13
+
+
+# ------------------------------------------------------------------ step
+STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (33, 17, 137), (20, 20, 161)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("impl,tile,col", [
+    (api.IMPL_PLAIN, 0, 0),
+    (api.IMPL_FUSED, 64, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 64, api.COLUMN_OUTBUF),
+    (api.IMPL_FUSED, 32, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 16, api.COLUMN_OUTBUF),
+    (api.IMPL_AUTO, 0, 0)], ids=["plain", "t64reg", "t64out", "t32reg", "t16out", "auto"])
+@pytest.mark.parametrize("dims", STEP_CASES, ids=lambda d: "x".join(map(str, d)))
+def test_step(dims, impl, tile, col, dtype):
+    ni, nj, nk = dims
+    if nk > api.stencil_max_fused_nk() and impl == api.IMPL_FUSED:
+        pytest.skip("longer than the fused classes (covered by plain/auto)")
+    print(f"step {dims} impl={impl} tile={tile} col={col} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=103)
+    r = _ref_inputs(f, dtype)
+    u, data, w = dev_fields(f, dtype, DEV)
+    out = fields.alloc(ni, nj, nk, dtype, DEV, fill=-3.0)
+    mask = fields.mask_tensor(dims, DEV)
+    coeff = c_scalar(inputs.COEFF, dtype)
+    api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask,
+                     opts=_opts(impl, tile, col, dtype, dims, api.OP_STEP))
+    torch.cuda.synchronize()
+    ref, mx, my = orc.step(r.u, r.data, r.w, coeff, inputs.DT_DZ, decide_f32=(dtype == torch.float32))
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
+    gmx, gmy = unpack_mask(mask, ni, nj, nk)
+    assert np.array_equal(gmx, mx) and np.array_equal(gmy, my)
+    full = host(fields.padded(out, ni, nj, nk))
+    ring = np.ones(full.shape, bool)
+    ring[:, 2:-2, 2:-2] = False
+    assert np.all(full[ring] == -3.0)
+
+
+def test_step_unaligned_and_strided_layouts():
+    """Fields with different pitches, origins and an offset vertical interval."""
+    ni, nj, nk = 77, 23, 19
+    f = inputs.fields_sized(ni, nj, nk, seed=104)
+    # u embedded in a bigger allocation: 3 extra levels below, odd pitch
+    big = torch.zeros((nk + 5, nj + 9, ni + 13), dtype=torch.float64, device=DEV)
+    big[3:3 + nk, 4 - 2:4 + nj + 2, 5 - 2:5 + ni + 2] = torch.as_tensor(f.u, device=DEV)
+    u = api.Field(big, (5, 4, 3))
+    data = fields.from_interior(f.data, torch.float64, DEV, aligned=False)
+    w = fields.from_interior(f.w, torch.float64, DEV, aligned=False)
+    out = fields.alloc(ni, nj, nk, torch.float64, DEV, aligned=False, fill=0.0)
+    api.stencil_step(u, data, w, out, (ni, nj, nk), inputs.COEFF, inputs.DT_DZ)
+    ref, _, _ = orc.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ)
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("wl", [inputs.STEP_256, inputs.STEP_512], ids=["256", "512"])
+def test_step_full_size(wl, dtype):
+    """The benchmark workloads at full size in the launch configuration the
+    benchmark times (fused, default tile), every output element checked."""
+    ni, nj, nk = wl.ni, wl.nj, wl.nk
+    print(f"step full {wl.name} {dtype}", flush=True)
+    f = inputs.fields_for(wl)
+    r = _ref_inputs(f, dtype)
+    u, data, w = dev_fields(f, dtype, DEV)
+    out = fields.alloc(ni, nj, nk, dtype, DEV, fill=0.0)
+    mask = fields.mask_tensor((ni, nj, nk), DEV)
+    api.stencil_step(u, data, w, out, (ni, nj, nk), inputs.COEFF, inputs.DT_DZ, mask=mask)
+    torch.cuda.synchronize()
+    ref, mx, my = orc.step(r.u, r.data, r.w, c_scalar(inputs.COEFF, dtype), inputs.DT_DZ,
+                           decide_f32=(dtype == torch.float32))
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
+    gmx, gmy = unpack_mask(mask, ni, nj, nk)
+    assert np.array_equal(gmx, mx) and np.array_equal(gmy, my)
+
+
+def test_empty_domains_leave_outputs_alone():
+    f = inputs.fields_sized(8, 8, 4, seed=105)
+    u, data, w = dev_fields(f, torch.float64, DEV)
+    out = fields.alloc(8, 8, 4, torch.float64, DEV, fill=5.0)
+    for dom in [(0, 8, 4), (8, 0, 4), (8, 8, 0)]:
+        api.stencil_step(u, data, w, out, dom, inputs.COEFF, inputs.DT_DZ)
+        api.stencil_hdiff(u, out, dom, inputs.COEFF)
+    torch.cuda.synchronize()
+    assert torch.all(out.tensor == 5.0)
