@@ -63,16 +63,10 @@
 #define MYIDX(i, j, k) ((size_t)(k) * (size_t)(nj + 1) * (size_t)ni + (size_t)((j) + 1) * (size_t)ni + (size_t)(i))
 
 /* The limiter (benchmark definition, Sec. 3.1): the flux is zeroed where
- * flux * gradient > 0.  Evaluated as a sign test, which equals the product
- * test in exact arithmetic and cannot be disturbed by underflow of f*g. */
-static int limiter_keeps(double f, double g) {
-  int zeroed = (f > 0.0 && g > 0.0) || (f < 0.0 && g < 0.0);
-  return !zeroed;
-}
-static int limiter_keeps_f32(float f, float g) {
-  int zeroed = (f > 0.0f && g > 0.0f) || (f < 0.0f && g < 0.0f);
-  return !zeroed;
-}
+ * flux * gradient > 0, the product taken literally in the precision of the
+ * decision (binary64, or binary32 when decide_f32 is set). */
+static int limiter_keeps(double f, double g) { return !(f * g > 0.0); }
+static int limiter_keeps_f32(float f, float g) { return !(f * g > 0.0f); }
 
 /* Laplacian stage, fixed association: 4u - ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])). */
 static double lap64(const double* u, int ni, int nj, int i, int j, int k) {
