@@ -94,8 +94,11 @@ typedef enum {
 
 typedef enum {
   STENCIL_COLUMN_AUTO = 0,
-  STENCIL_COLUMN_REGISTERS = 1, /* elimination factors of a column in VGPRs */
-  STENCIL_COLUMN_OUTBUF = 2     /* c' in VGPRs, d' staged in the output field */
+  STENCIL_COLUMN_REGISTERS = 1, /* one lane per column, its factors in VGPRs */
+  STENCIL_COLUMN_OUTBUF = 2,    /* one lane per column, c' in VGPRs, d' staged in out */
+  STENCIL_COLUMN_SPLIT = 3      /* two lanes per column eliminating from both ends,
+                                   each holding half the factors in VGPRs (fused
+                                   step: nk <= 80 in FP64, <= 160 in FP32) */
 } stencil_column_store;
 
 /* Optional per-call options; pass NULL for defaults. */

@@ -31,7 +31,7 @@ ERRORS = {
 CODES = {v: k for k, v in ERRORS.items()}
 
 IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN = 0, 1, 2
-COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF = 0, 1, 2
+COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF, COLUMN_SPLIT = 0, 1, 2, 3
 OP_HDIFF, OP_VADV, OP_STEP, OP_HDIFF_ADJOINT, OP_VADV_ADJOINT, OP_STEP_ADJOINT = range(6)
 
 I64x3 = ctypes.c_int64 * 3

@@ -16,13 +16,13 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, F32, F64, IMPL_AUTO, IMPL_FUSED,
+from ._lib import (COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
                    IMPL_PLAIN, OP_HDIFF, OP_HDIFF_ADJOINT, OP_STEP, OP_STEP_ADJOINT, OP_VADV,
                    OP_VADV_ADJOINT, StencilError)
 
 __all__ = [
     "Field", "Options", "StencilError", "F32", "F64",
-    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF",
+    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
     "OP_HDIFF", "OP_VADV", "OP_STEP", "OP_HDIFF_ADJOINT", "OP_VADV_ADJOINT", "OP_STEP_ADJOINT",
     "stencil_version", "stencil_last_error", "stencil_max_fused_nk", "stencil_mask_bytes",
     "stencil_workspace_bytes", "stencil_hdiff", "stencil_vadv", "stencil_step",

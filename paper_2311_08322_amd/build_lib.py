@@ -36,6 +36,9 @@ def _units():
             for col in cols:
                 u.append(("k_step_inst.hip", f"step_{t}_{ti}_c{col}",
                           [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", f"-DGT4MI_COL={col}", *UNROLL]))
+        for ti in (64, 32, 16):
+            u.append(("k_step_inst.hip", f"split_{t}_{ti}",
+                      [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", *UNROLL]))
         for col in cols:
             u.append(("k_step_inst.hip", f"vadv_{t}_c{col}",
                       [f"-DGT4MI_T={t}", "-DGT4MI_VADV", f"-DGT4MI_COL={col}", *UNROLL]))
@@ -46,11 +49,11 @@ def _units():
     return u
 
 
-def _compile(unit) -> str:
+def _compile(unit, build_dir=BUILD, defines=()) -> str:
     src, name, extra = unit
-    obj = os.path.join(BUILD, name + ".o")
+    obj = os.path.join(build_dir, name + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *defines, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -58,22 +61,25 @@ def _compile(unit) -> str:
     return f"{name}: {time.time() - t:.1f}s"
 
 
-def build(verbose: bool = True, jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, jobs: int | None = None, out: str = LIB, build_dir: str = BUILD,
+          defines=()) -> str:
+    """Compile every unit and link `out`.  `defines` (e.g. -DGT4MI_PD=4)
+    select compile-time variants of the kernels for tuning experiments."""
+    os.makedirs(build_dir, exist_ok=True)
     units = _units()
     jobs = jobs or max(1, min(len(units), os.cpu_count() or 4))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        for msg in ex.map(_compile, units):
+        for msg in ex.map(lambda u: _compile(u, build_dir, tuple(defines)), units):
             if verbose:
                 print("  built", msg, flush=True)
-    objs = [os.path.join(BUILD, name + ".o") for _, name, _ in units]
-    tmp = LIB + ".tmp%d" % os.getpid()
+    objs = [os.path.join(build_dir, name + ".o") for _, name, _ in units]
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -111,6 +111,9 @@ int check_field(const char* name, const stencil_field* f, const int64_t* dom, Ro
                 (long long)f->stride[1], (long long)f->shape[0]);
   if (f->stride[2] < f->stride[1] * f->shape[1] || f->stride[2] >= (int64_t(1) << 46))
     return fail(STENCIL_E_STRIDE, "%s.stride[2] = %lld overlaps planes", name, (long long)f->stride[2]);
+  // kernels address within a level with 32-bit byte offsets
+  if ((f->stride[1] * f->shape[1] + f->shape[0]) * (int64_t)es >= (int64_t(1) << 32))
+    return fail(STENCIL_E_UNSUPPORTED, "%s: one level spans 4 GiB or more", name);
   const int64_t h = (role == ROLE_HALO) ? kHalo : 0;
   for (int d = 0; d < 2; ++d) {
     if (f->origin[d] < h)
@@ -141,8 +144,12 @@ ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, co
   tuning_get(dt, op, dom, &ti, &tj, &col);
   r.tile_i = (o && o->tile_i) ? o->tile_i : ti;
   r.column_store = (o && o->column_store) ? o->column_store : col;
-  if (r.column_store == STENCIL_COLUMN_AUTO)
-    r.column_store = (dt == STENCIL_F64 && dom[2] > 96) ? STENCIL_COLUMN_OUTBUF : STENCIL_COLUMN_REGISTERS;
+  if (r.column_store == STENCIL_COLUMN_AUTO) {
+    if (op == STENCIL_OP_STEP && dom[2] <= (dt == STENCIL_F64 ? 80 : 160))
+      r.column_store = STENCIL_COLUMN_SPLIT;
+    else
+      r.column_store = (dt == STENCIL_F64 && dom[2] > 96) ? STENCIL_COLUMN_OUTBUF : STENCIL_COLUMN_REGISTERS;
+  }
   r.ws = o ? o->workspace : nullptr;
   r.ws_bytes = o ? o->workspace_bytes : 0;
   return r;
@@ -157,7 +164,7 @@ int check_opts(const stencil_options* o) {
       !(o->tile_i == 16 && (o->tile_j == 16 || o->tile_j == 0)))
     return fail(STENCIL_E_ARG, "options tile %dx%d unsupported (64x4, 32x8, 16x16)", (int)o->tile_i,
                 (int)o->tile_j);
-  if (o->column_store < 0 || o->column_store > STENCIL_COLUMN_OUTBUF)
+  if (o->column_store < 0 || o->column_store > STENCIL_COLUMN_SPLIT)
     return fail(STENCIL_E_ARG, "options.column_store = %d unknown", (int)o->column_store);
   if (o->workspace_bytes && !o->workspace) return fail(STENCIL_E_NULL, "options.workspace is NULL");
   return STENCIL_OK;

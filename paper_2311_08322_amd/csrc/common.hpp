@@ -45,19 +45,62 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   return x * q + (x < r ? x : r) + local;
 }
 
-// ------------------------------------------------------------ limiter
-// The flux is zeroed where flux * gradient > 0 (Sec. 3.1 benchmark
-// definition), taken as a sign test so that underflow of the product
-// cannot flip it.
-template <typename T>
-__device__ __forceinline__ bool flux_kept(T f, T g) {
-  const bool zeroed = (f > T(0) && g > T(0)) || (f < T(0) && g < T(0));
-  return !zeroed;
+// ------------------------------------------------------------ addressing
+// Fields are read and written through buffer resources: a per-level
+// descriptor (uniform, SGPRs: base of the level and the byte size of the
+// window the kernel may touch) plus a per-lane 32-bit byte offset.  A level
+// change is a scalar add; accesses beyond the window read 0 / are dropped
+// by the hardware range check instead of reaching other memory.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data, no swizzle
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
+// One field as seen by a kernel: the level-0 base, the level stride (bytes)
+// and the window (bytes) of one level.
+struct LevelView {
+  const char* base;
+  int64_t level_bytes;
+  uint32_t window;
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t at(int k) const {
+    return make_rsrc(base + (int64_t)k * level_bytes, window);
+  }
+};
+
+// ------------------------------------------------------------ limiter
+// The flux is zeroed where flux * gradient > 0 (Sec. 3.1 benchmark
+// definition), the product taken literally in the working precision.
 template <typename T>
-__device__ __forceinline__ T recip(T m) {
-  return T(1) / m;
+__device__ __forceinline__ bool flux_kept(T f, T g) {
+  return !(f * g > T(0));
+}
+
+// Reciprocal of a Thomas pivot.  The pivots are bounded (m >= 1, strict
+// diagonal dominance), so the hardware reciprocal refined by Newton steps
+// (two for binary64, one for binary32) is accurate to about an ulp.
+__device__ __forceinline__ double recip(double m) {
+  double r = __builtin_amdgcn_rcp(m);
+  r = __builtin_fma(__builtin_fma(-m, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-m, r, 1.0), r, r);
+  return r;
+}
+__device__ __forceinline__ float recip(float m) {
+  float r = __builtin_amdgcn_rcpf(m);
+  return __builtin_fmaf(__builtin_fmaf(-m, r, 1.0f), r, r);
 }
 
 // ------------------------------------------------------------ argument blocks

@@ -10,8 +10,9 @@
 // PARALLEL, the elimination FORWARD and the substitution BACKWARD; fusing
 // them keeps the "as if in program order" meaning because each stage reads
 // only values the previous stage has completed for this tile and level.
-// The temporaries (lap, fluxes, c', d') never leave the chip: lap and the
-// u-tile live in LDS, c'/d' of a column in the lane's VGPRs (unrolled k).
+// The temporaries (lap, fluxes, c', d') never leave the chip: the u-tile of
+// a level lives in LDS, lap and the fluxes in registers, c'/d' of a column
+// in the lane's VGPRs (the k loop is unrolled per register class).
 #pragma once
 
 #include "common.hpp"
@@ -23,8 +24,7 @@ __device__ __forceinline__ float absv(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double absv(double x) { return __builtin_fabs(x); }
 
 template <int TI>
-__device__ __forceinline__ void store_row_bits(uint8_t* row, int i0, uint64_t bits) {
-  uint8_t* p = row + (i0 >> 3);
+__device__ __forceinline__ void store_row_bits(uint8_t* p, uint64_t bits) {
   if constexpr (TI == 64) {
     *reinterpret_cast<uint64_t*>(p) = bits;
   } else if constexpr (TI == 32) {
@@ -35,63 +35,121 @@ __device__ __forceinline__ void store_row_bits(uint8_t* row, int i0, uint64_t bi
   }
 }
 
-// Record the limiter decisions of one level.  Every lane of the wave must
-// call this (ballots).  A wave covers 64/TI rows of TI columns.
-template <typename T, int TI>
-__device__ __forceinline__ void record_mask(const StepArgs<T>& A, int k, int i0, int i, int j,
-                                            bool active, bool kxr, bool kyr, bool kxl, bool kyl) {
-  const uint64_t bx = __ballot(active && kxr);
-  const uint64_t by = __ballot(active && kyr);
-  const int lane = threadIdx.x & 63;
-  if ((lane % TI) == 0 && j < A.nj) {
-    const int sh = (lane / TI) * TI;
-    const int64_t row = ((int64_t)k * A.nj + j) * A.ml.words * 8;
-    store_row_bits<TI>(A.mask + A.ml.x_off + row, i0, bx >> sh);
-    store_row_bits<TI>(A.mask + A.ml.y_off + row, i0, by >> sh);
-  }
-  if (active && i == 0) A.mask[A.ml.ex_off + (int64_t)k * A.nj + j] = kxl ? 1 : 0;
-  if (active && j == 0) A.mask[A.ml.ey_off + (int64_t)k * A.ni + i] = kyl ? 1 : 0;
-}
+// Where one lane records the limiter decisions of its tile row (level 0;
+// level k adds k planes).  A wave covers 64/TI rows of TI columns: the
+// row's first lane stores the row's TI bits of the X and Y planes, the
+// lanes on the domain's i = 0 / j = 0 edges store the edge bytes.
+struct MaskWriter {
+  uint8_t* xrow;  // X-plane bytes of this row at i0 (null: lane stores no row)
+  uint8_t* ex;    // X-edge byte of (j) (null unless i == 0)
+  uint8_t* ey;    // Y-edge byte of (i) (null unless j == 0)
+  int64_t plane, ex_plane, ey_plane, y_minus_x;
+  int shift;
 
-// Horizontal diffusion of the lane's own point at one level, from the
-// u-tile (with halo) and the lap tile in LDS.  Returns out; the four flux
+  template <typename T, int TI>
+  __device__ __forceinline__ static MaskWriter make(const StepArgs<T>& A, int i0, int i, int j, bool active) {
+    MaskWriter m;
+    const int lane = threadIdx.x & 63;
+    m.shift = (lane / TI) * TI;
+    m.plane = (int64_t)A.nj * A.ml.words * 8;
+    m.ex_plane = A.nj;
+    m.ey_plane = A.ni;
+    m.y_minus_x = A.ml.y_off - A.ml.x_off;
+    m.xrow = ((lane % TI) == 0 && j < A.nj) ? A.mask + A.ml.x_off + (int64_t)j * A.ml.words * 8 + (i0 >> 3) : nullptr;
+    m.ex = (active && i == 0) ? A.mask + A.ml.ex_off + j : nullptr;
+    m.ey = (active && j == 0) ? A.mask + A.ml.ey_off + i : nullptr;
+    return m;
+  }
+
+  // every lane of the wave must call this (ballots)
+  template <int TI>
+  __device__ __forceinline__ void record(int k, bool active, bool kxr, bool kyr, bool kxl, bool kyl) const {
+    const uint64_t bx = __ballot(active && kxr);
+    const uint64_t by = __ballot(active && kyr);
+    if (xrow) {
+      uint8_t* p = xrow + (int64_t)k * plane;
+      store_row_bits<TI>(p, bx >> shift);
+      store_row_bits<TI>(p + y_minus_x, by >> shift);
+    }
+    if (ex) ex[(int64_t)k * ex_plane] = kxl ? 1 : 0;
+    if (ey) ey[(int64_t)k * ey_plane] = kyl ? 1 : 0;
+  }
+};
+
+// Horizontal diffusion of one point from the u-tile in LDS.  `c` points at
+// the lane's own u(i,j); HI is the tile's row pitch.  The five Laplacians
+// the point needs are formed from its 13-point diamond (no shared lap
+// stage, so one barrier per level suffices).  Returns out; the four flux
 // decisions go to kxr/kxl/kyr/kyl (right/left, x/y).
-template <typename T, int TI, int TJ>
-__device__ __forceinline__ T hdiff_point(const T* __restrict__ U, const T* __restrict__ Lp, int ti,
-                                         int tj, T coeff, bool& kxr, bool& kxl, bool& kyr,
-                                         bool& kyl) {
-  constexpr int HI = TI + 4, LI = TI + 2;
-  const int cu = (tj + 2) * HI + (ti + 2);
-  const int cl = (tj + 1) * LI + (ti + 1);
-  const T uc = U[cu], lc = Lp[cl];
-  const T fxr = Lp[cl + 1] - lc, gxr = U[cu + 1] - uc;
-  const T fxl = lc - Lp[cl - 1], gxl = uc - U[cu - 1];
-  const T fyr = Lp[cl + LI] - lc, gyr = U[cu + HI] - uc;
-  const T fyl = lc - Lp[cl - LI], gyl = uc - U[cu - HI];
-  kxr = flux_kept(fxr, gxr);
-  kxl = flux_kept(fxl, gxl);
-  kyr = flux_kept(fyr, gyr);
-  kyl = flux_kept(fyl, gyl);
+template <typename T, int HI>
+__device__ __forceinline__ T hdiff_diamond(const T* __restrict__ c, T coeff, bool& kxr, bool& kxl,
+                                           bool& kyr, bool& kyl) {
+  const T u00 = c[0], um1 = c[-1], up1 = c[1], um2 = c[-2], up2 = c[2];
+  const T vm1 = c[-HI], vp1 = c[HI], vm2 = c[-2 * HI], vp2 = c[2 * HI];
+  const T mm = c[-HI - 1], mp = c[-HI + 1], pm = c[HI - 1], pp = c[HI + 1];
+  // lap = 4u - ((u[i-1] + u[i+1]) + (u[j-1] + u[j+1])) at (0,0), (+-1,0), (0,+-1)
+  const T L00 = T(4) * u00 - ((um1 + up1) + (vm1 + vp1));
+  const T Lp0 = T(4) * up1 - ((u00 + up2) + (mp + pp));
+  const T Lm0 = T(4) * um1 - ((um2 + u00) + (mm + pm));
+  const T L0p = T(4) * vp1 - ((pm + pp) + (u00 + vp2));
+  const T L0m = T(4) * vm1 - ((mm + mp) + (vm2 + u00));
+  const T fxr = Lp0 - L00, fxl = L00 - Lm0, fyr = L0p - L00, fyl = L00 - L0m;
+  kxr = flux_kept(fxr, up1 - u00);
+  kxl = flux_kept(fxl, u00 - um1);
+  kyr = flux_kept(fyr, vp1 - u00);
+  kyl = flux_kept(fyl, u00 - vm1);
   const T Fxr = kxr ? fxr : T(0), Fxl = kxl ? fxl : T(0);
   const T Fyr = kyr ? fyr : T(0), Fyl = kyl ? fyl : T(0);
-  return uc - coeff * ((Fxr - Fxl) + (Fyr - Fyl));
+  return u00 - coeff * ((Fxr - Fxl) + (Fyr - Fyl));
 }
 
-// lap = 4u - ((u[i-1] + u[i+1]) + (u[j-1] + u[j+1])) on the (TI+2) x (TJ+2)
-// box around the tile.
+// Level-invariant addressing of a TI x TJ tile: byte offsets of the
+// lane's share of the (TI+4) x (TJ+4) u-tile from the level base at padded
+// point (-2,-2), and of its own column in the interior fields.  Lanes
+// outside a ragged domain edge are clamped onto valid points: they load
+// (and compute) garbage that is never stored, with no per-level branches.
 template <typename T, int TI, int TJ>
-__device__ __forceinline__ void lap_tile(const T* __restrict__ U, T* __restrict__ Lp, int tid) {
-  constexpr int NT = TI * TJ, HI = TI + 4, LI = TI + 2, LN = (TI + 2) * (TJ + 2);
+struct TileAddr {
+  static constexpr int NT = TI * TJ, HI = TI + 4, HN = (TI + 4) * (TJ + 4);
+  static constexpr int NLD = (HN + NT - 1) / NT;
+  uint32_t hoff[NLD];
+  int ti, tj, i0, j0, i, j, ic, jc;
+  bool active;
+
+  __device__ __forceinline__ void init(int tile, int tiles_i, int ni, int nj, int64_t u_sj) {
+    init_lane(threadIdx.x, tile, tiles_i, ni, nj, u_sj);
+  }
+  // `tid`: the lane's index among the NT lanes that share the tile
+  __device__ __forceinline__ void init_lane(int tid, int tile, int tiles_i, int ni, int nj, int64_t u_sj) {
+    ti = tid % TI;
+    tj = tid / TI;
+    const int bi = tile % tiles_i, bj = tile / tiles_i;
+    i0 = bi * TI;
+    j0 = bj * TJ;
+    i = i0 + ti;
+    j = j0 + tj;
+    active = (i < ni) && (j < nj);
+    ic = min(i, ni - 1);
+    jc = min(j, nj - 1);
 #pragma unroll
-  for (int q = 0; q < (LN + NT - 1) / NT; ++q) {
-    const int e = tid + q * NT;
-    if (e < LN) {
-      const int lj = e / LI, li = e - lj * LI;
-      const int c = (lj + 1) * HI + (li + 1);
-      const T s = (U[c - 1] + U[c + 1]) + (U[c - HI] + U[c + HI]);
-      Lp[e] = T(4) * U[c] - s;
+    for (int q = 0; q < NLD; ++q) {
+      const int e = min(tid + q * NT, HN - 1);
+      const int hj = e / HI, hi = e - hj * HI;
+      const int gi = min(i0 + hi, ni + 3), gj = min(j0 + hj, nj + 3);  // padded coordinates
+      hoff[q] = ((uint32_t)gi + (uint32_t)gj * (uint32_t)u_sj) * (uint32_t)sizeof(T);
     }
   }
+};
+
+// Buffer view of a field whose pointer `p` is at domain point (0,0,0),
+// with the window starting at (di, dj) relative to it and `rows` rows long.
+template <typename T>
+__device__ __forceinline__ LevelView level_view(const T* p, int64_t sj, int64_t sk, int di, int dj, int rows) {
+  LevelView v;
+  v.base = reinterpret_cast<const char*>(p + di + (int64_t)dj * sj);
+  v.level_bytes = sk * (int64_t)sizeof(T);
+  v.window = (uint32_t)(sj * rows * (int64_t)sizeof(T));
+  return v;
 }
 
 // ------------------------------------------------------------------ step
@@ -99,43 +157,34 @@ __device__ __forceinline__ void lap_tile(const T* __restrict__ U, T* __restrict_
 // COL = 2: c' in registers, d' staged in `out` (read back by the same lane).
 template <typename T, int TI, int TJ, int NKMAX, int PD, int COL>
 __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
-  constexpr int NT = TI * TJ;
-  constexpr int HI = TI + 4, HN = (TI + 4) * (TJ + 4);
-  constexpr int LN = (TI + 2) * (TJ + 2);
-  constexpr int NLD = (HN + NT - 1) / NT;
+  using TA = TileAddr<T, TI, TJ>;
+  constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
   static_assert(NT == kWG, "tile must hold 256 columns");
-  __shared__ T su[2][HN];
-  __shared__ T sl[LN];
+  __shared__ T su[2][NLD * NT];  // padded: every lane's store lands inside
 
-  const int tid = threadIdx.x, ti = tid % TI, tj = tid / TI;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int bi = tile % A.tiles_i, bj = tile / A.tiles_i;
-  const int i0 = bi * TI, j0 = bj * TJ, i = i0 + ti, j = j0 + tj;
-  const bool active = (i < A.ni) && (j < A.nj);
-  const int nk = A.nk;
+  TA t;
+  t.init(xcd_tile(blockIdx.x, gridDim.x), A.tiles_i, A.ni, A.nj, A.u_sj);
+  const int nk = A.nk, tid = threadIdx.x;
+  constexpr uint32_t S = sizeof(T);
+  const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, -2, -2, A.nj + 4);
+  const LevelView vd = level_view(A.data, A.d_sj, A.d_sk, 0, 0, A.nj);
+  const LevelView vw = level_view(A.w, A.w_sj, A.w_sk, 0, 0, A.nj);
+  const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
+  const uint32_t doff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.d_sj) * S;
+  const uint32_t woff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.w_sj) * S;
+  const uint32_t ooff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.o_sj) * S;
+  const bool active = t.active;
+  MaskWriter mw;
+  if (A.mask) mw = MaskWriter::make<T, TI>(A, t.i0, t.i, t.j, active);
 
-  // halo-tile load plan
-  int64_t hoff[NLD];
-  bool hok[NLD];
-#pragma unroll
-  for (int q = 0; q < NLD; ++q) {
-    const int e = tid + q * NT;
-    const int hj = e / HI, hi = e - hj * HI;
-    const int gi = i0 - 2 + hi, gj = j0 - 2 + hj;
-    hok[q] = (e < HN) && (gi < A.ni + 2) && (gj < A.nj + 2);
-    hoff[q] = hok[q] ? (int64_t)gi + (int64_t)gj * A.u_sj : 0;
-  }
-  const int64_t doff = active ? (int64_t)i + (int64_t)j * A.d_sj : 0;
-  const int64_t woff = active ? (int64_t)i + (int64_t)j * A.w_sj : 0;
-  const int64_t ooff = (int64_t)i + (int64_t)j * A.o_sj;
-
-  // prefetch ring: slot k % PD holds level k
+  // prefetch ring: slot k % PD holds level k (u-tile share, data_k, w_{k+1})
   T pu[PD][NLD], pd[PD], pw[PD];
   auto issue = [&](int s, int k) {
+    const auto ru = vu.at(k);
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) pu[s][q] = hok[q] ? A.u[hoff[q] + (int64_t)k * A.u_sk] : T(0);
-    pd[s] = active ? A.data[doff + (int64_t)k * A.d_sk] : T(0);
-    pw[s] = (active && k + 1 < nk) ? A.w[woff + (int64_t)(k + 1) * A.w_sk] : T(0);
+    for (int q = 0; q < NLD; ++q) pu[s][q] = buf_ld(ru, t.hoff[q], T());
+    pd[s] = buf_ld(vd.at(k), doff, T());
+    pw[s] = buf_ld(vw.at(k + 1), woff, T());  // w has nk+1 levels
   };
 #pragma unroll
   for (int s = 0; s < PD; ++s)
@@ -145,6 +194,7 @@ __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
   T dp[COL == 1 ? NKMAX : 1];
   T wk = T(0), cprev = T(0), dprev = T(0);
   const T coeff = A.coeff, r4 = A.r4;
+  const int cu = (t.tj + 2) * HI + (t.ti + 2);
 
 #pragma unroll
   for (int k = 0; k < NKMAX; ++k) {
@@ -152,16 +202,13 @@ __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
       const int s = k % PD;
       T* U = su[k & 1];
 #pragma unroll
-      for (int q = 0; q < NLD; ++q)
-        if (tid + q * NT < HN) U[tid + q * NT] = pu[s][q];
+      for (int q = 0; q < NLD; ++q) U[tid + q * NT] = pu[s][q];
       const T dk = pd[s], wk1 = pw[s];
       if (k + PD < nk) issue(s, k + PD);
       __syncthreads();
-      lap_tile<T, TI, TJ>(U, sl, tid);
-      __syncthreads();
       bool kxr, kxl, kyr, kyl;
-      const T h = hdiff_point<T, TI, TJ>(U, sl, ti, tj, coeff, kxr, kxl, kyr, kyl);
-      if (A.mask) record_mask<T, TI>(A, k, i0, i, j, active, kxr, kyr, kxl, kyl);
+      const T h = hdiff_diamond<T, HI>(U + cu, coeff, kxr, kxl, kyr, kyl);
+      if (A.mask) mw.record<TI>(k, active, kxr, kyr, kxl, kyl);
       // Thomas forward elimination, coefficients rebuilt from w
       const T a = (k > 0) ? -r4 * wk : T(0);
       const T c = (k < nk - 1) ? r4 * wk1 : T(0);
@@ -173,7 +220,7 @@ __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
       if constexpr (COL == 1) {
         dp[k] = dprev;
       } else {
-        if (active) A.out[ooff + (int64_t)k * A.o_sk] = dprev;
+        if (active) buf_st(vo.at(k), ooff, dprev);
       }
       wk = wk1;
     }
@@ -183,16 +230,13 @@ __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
 #pragma unroll
   for (int k = NKMAX - 1; k >= 0; --k) {
     if (k < nk) {
-      T* o = A.out + ooff + (int64_t)k * A.o_sk;
+      const auto ro = vo.at(k);
       if constexpr (COL == 1) {
         x = dp[k] - cp[k] * x;
-        if (active) *o = x;
       } else {
-        if (active) {
-          x = *o - cp[k] * x;
-          *o = x;
-        }
+        x = buf_ld(ro, ooff, T()) - cp[k] * x;
       }
+      if (active) buf_st(ro, ooff, x);
     }
   }
 }
@@ -207,15 +251,20 @@ __global__ void __launch_bounds__(kWG) k_vadv_fused(StepArgs<T> A) {
   const int i = bi * 64 + (threadIdx.x & 63), j = bj * 4 + (threadIdx.x >> 6);
   if (i >= A.ni || j >= A.nj) return;
   const int nk = A.nk;
-  const int64_t uoff = (int64_t)i + (int64_t)j * A.u_sj;
-  const int64_t doff = (int64_t)i + (int64_t)j * A.d_sj;
-  const int64_t woff = (int64_t)i + (int64_t)j * A.w_sj;
-  const int64_t ooff = (int64_t)i + (int64_t)j * A.o_sj;
+  constexpr uint32_t S = sizeof(T);
+  const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, 0, 0, A.nj);
+  const LevelView vd = level_view(A.data, A.d_sj, A.d_sk, 0, 0, A.nj);
+  const LevelView vw = level_view(A.w, A.w_sj, A.w_sk, 0, 0, A.nj);
+  const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
+  const uint32_t uoff = ((uint32_t)i + (uint32_t)j * (uint32_t)A.u_sj) * S;
+  const uint32_t doff = ((uint32_t)i + (uint32_t)j * (uint32_t)A.d_sj) * S;
+  const uint32_t woff = ((uint32_t)i + (uint32_t)j * (uint32_t)A.w_sj) * S;
+  const uint32_t ooff = ((uint32_t)i + (uint32_t)j * (uint32_t)A.o_sj) * S;
   T pu[PD], pd[PD], pw[PD];
   auto issue = [&](int s, int k) {
-    pu[s] = A.u[uoff + (int64_t)k * A.u_sk];
-    pd[s] = A.data[doff + (int64_t)k * A.d_sk];
-    pw[s] = (k + 1 < nk) ? A.w[woff + (int64_t)(k + 1) * A.w_sk] : T(0);
+    pu[s] = buf_ld(vu.at(k), uoff, T());
+    pd[s] = buf_ld(vd.at(k), doff, T());
+    pw[s] = buf_ld(vw.at(k + 1), woff, T());  // w has nk+1 levels
   };
 #pragma unroll
   for (int s = 0; s < PD; ++s)
@@ -238,7 +287,7 @@ __global__ void __launch_bounds__(kWG) k_vadv_fused(StepArgs<T> A) {
       dprev = (dk - a * dprev) * inv;
       cp[k] = cprev;
       if constexpr (COL == 1) dp[k] = dprev;
-      else A.out[ooff + (int64_t)k * A.o_sk] = dprev;
+      else buf_st(vo.at(k), ooff, dprev);
       wk = wk1;
     }
   }
@@ -246,66 +295,61 @@ __global__ void __launch_bounds__(kWG) k_vadv_fused(StepArgs<T> A) {
 #pragma unroll
   for (int k = NKMAX - 1; k >= 0; --k) {
     if (k < nk) {
-      T* o = A.out + ooff + (int64_t)k * A.o_sk;
+      const auto ro = vo.at(k);
       if constexpr (COL == 1) x = dp[k] - cp[k] * x;
-      else x = *o - cp[k] * x;
-      *o = x;
+      else x = buf_ld(ro, ooff, T()) - cp[k] * x;
+      buf_st(ro, ooff, x);
     }
   }
 }
 
 // ------------------------------------------------------------------ hdiff
-// Tile marched over the levels [k0, k1) of the launch, next level's u-tile
-// prefetched in registers while the current one is computed.
+// Tile marched over the levels [kbeg, kend) of its workgroup, the next
+// level's u-tile prefetched in registers while the current one is computed.
 template <typename T, int TI, int TJ>
 __global__ void __launch_bounds__(TI* TJ) k_hdiff_fused(StepArgs<T> A) {
-  constexpr int NT = TI * TJ;
-  constexpr int HI = TI + 4, HN = (TI + 4) * (TJ + 4);
-  constexpr int LN = (TI + 2) * (TJ + 2);
-  constexpr int NLD = (HN + NT - 1) / NT;
-  __shared__ T su[2][HN];
-  __shared__ T sl[LN];
-  const int tid = threadIdx.x, ti = tid % TI, tj = tid / TI;
-  const int tile = xcd_tile(blockIdx.x, A.ntiles) ;
-  const int bi = tile % A.tiles_i, bj = tile / A.tiles_i;
-  const int i0 = bi * TI, j0 = bj * TJ, i = i0 + ti, j = j0 + tj;
-  const bool active = (i < A.ni) && (j < A.nj);
-  const int kb = blockIdx.y;
-  const int kbeg = A.k0 + kb * A.k1, kend = min(kbeg + A.k1, A.nk);  // k1 = levels per block
-  int64_t hoff[NLD];
-  bool hok[NLD];
-#pragma unroll
-  for (int q = 0; q < NLD; ++q) {
-    const int e = tid + q * NT;
-    const int hj = e / HI, hi = e - hj * HI;
-    const int gi = i0 - 2 + hi, gj = j0 - 2 + hj;
-    hok[q] = (e < HN) && (gi < A.ni + 2) && (gj < A.nj + 2);
-    hoff[q] = hok[q] ? (int64_t)gi + (int64_t)gj * A.u_sj : 0;
-  }
-  const int64_t ooff = (int64_t)i + (int64_t)j * A.o_sj;
+  using TA = TileAddr<T, TI, TJ>;
+  constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
+  __shared__ T su[2][NLD * NT];
+  TA t;
+  t.init(xcd_tile(blockIdx.x, gridDim.x), A.tiles_i, A.ni, A.nj, A.u_sj);
+  const int tid = threadIdx.x;
+  const int kbeg = blockIdx.y * A.k1, kend = min(kbeg + A.k1, A.nk);  // k1: levels per workgroup
+  const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, -2, -2, A.nj + 4);
+  const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
+  const uint32_t ooff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.o_sj) * (uint32_t)sizeof(T);
+  const bool active = t.active;
+  MaskWriter mw;
+  if (A.mask) mw = MaskWriter::make<T, TI>(A, t.i0, t.i, t.j, active);
+  const int cu = (t.tj + 2) * HI + (t.ti + 2);
   T pu[NLD];
+  {
+    const auto ru = vu.at(kbeg);
 #pragma unroll
-  for (int q = 0; q < NLD; ++q) pu[q] = (hok[q] && kbeg < kend) ? A.u[hoff[q] + (int64_t)kbeg * A.u_sk] : T(0);
+    for (int q = 0; q < NLD; ++q) pu[q] = buf_ld(ru, t.hoff[q], T());
+  }
   for (int k = kbeg; k < kend; ++k) {
     T* U = su[k & 1];
 #pragma unroll
-    for (int q = 0; q < NLD; ++q)
-      if (tid + q * NT < HN) U[tid + q * NT] = pu[q];
+    for (int q = 0; q < NLD; ++q) U[tid + q * NT] = pu[q];
     if (k + 1 < kend) {
+      const auto ru = vu.at(k + 1);
 #pragma unroll
-      for (int q = 0; q < NLD; ++q) pu[q] = hok[q] ? A.u[hoff[q] + (int64_t)(k + 1) * A.u_sk] : T(0);
+      for (int q = 0; q < NLD; ++q) pu[q] = buf_ld(ru, t.hoff[q], T());
     }
     __syncthreads();
-    lap_tile<T, TI, TJ>(U, sl, tid);
-    __syncthreads();
     bool kxr, kxl, kyr, kyl;
-    const T h = hdiff_point<T, TI, TJ>(U, sl, ti, tj, A.coeff, kxr, kxl, kyr, kyl);
-    if (A.mask) record_mask<T, TI>(A, k, i0, i, j, active, kxr, kyr, kxl, kyl);
-    if (active) A.out[ooff + (int64_t)k * A.o_sk] = h;
+    const T h = hdiff_diamond<T, HI>(U + cu, A.coeff, kxr, kxl, kyr, kyl);
+    if (A.mask) mw.record<TI>(k, active, kxr, kyr, kxl, kyl);
+    if (active) buf_st(vo.at(k), ooff, h);
   }
 }
 
 // ------------------------------------------------------------------ class dispatch
+#ifndef GT4MI_PD
+#define GT4MI_PD 2  // levels of u/data/w loaded ahead of the one being computed
+#endif
+
 // One instantiation per register class of the column length.  The list of
 // classes is shared by the forward and adjoint column kernels.
 #define GT4MI_NK_CLASSES(X) X(16) X(32) X(48) X(64) X(80) X(96) X(128) X(160)
@@ -322,7 +366,7 @@ hipError_t launch_step_classes(const StepArgs<T>& A, hipStream_t s) {
 #define GT4MI_STEP_CASE(N)                                                             \
   if constexpr (column_class_ok<T, COL>(N)) {                                          \
     if (A.nk <= N) {                                                                   \
-      hipLaunchKernelGGL((k_step_fused<T, TI, TJ, N, 2, COL>), grid, block, 0, s, A); \
+      hipLaunchKernelGGL((k_step_fused<T, TI, TJ, N, GT4MI_PD, COL>), grid, block, 0, s, A); \
       return hipGetLastError();                                                        \
     }                                                                                  \
   }

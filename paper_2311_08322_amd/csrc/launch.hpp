@@ -18,6 +18,8 @@ template <typename T, int TI, int TJ, int COL>
 hipError_t launch_step_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int COL>
 hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
+template <typename T, int TI, int TJ>
+hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T>
 hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s);
 template <typename T>

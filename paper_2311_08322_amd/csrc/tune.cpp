@@ -147,9 +147,10 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   };
   std::vector<Cand> cands;
   for (int t : {64, 32, 16}) {
-    if (op == STENCIL_OP_STEP && dtype == STENCIL_F64 && nk <= 96) {
-      cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS});
-      cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF});
+    if (op == STENCIL_OP_STEP) {
+      if (nk <= (dtype == STENCIL_F64 ? 80 : 160)) cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT});
+      if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS});
+      if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF});
     } else {
       cands.push_back({t, 256 / t, STENCIL_COLUMN_AUTO});
     }
@@ -281,7 +282,7 @@ int stencil_load_tuning(const char* path) {
       return fail(STENCIL_E_ARG, "%s: malformed entry", path);
     if (!((v.tile_i == 64 && v.tile_j == 4) || (v.tile_i == 32 && v.tile_j == 8) ||
           (v.tile_i == 16 && v.tile_j == 16)) ||
-        v.col < 0 || v.col > STENCIL_COLUMN_OUTBUF)
+        v.col < 0 || v.col > STENCIL_COLUMN_SPLIT)
       return fail(STENCIL_E_ARG, "%s: entry with unsupported tile or column store", path);
     const char* us = strstr(p, "\"us\":");
     if (us && us < e) v.us = strtod(us + 5, nullptr);

@@ -22,7 +22,9 @@ def _forward(f, dtype, dims):
     ni, nj, nk = dims
     out = fields.alloc(ni, nj, nk, dtype, DEV, fill=0.0)
     mask = fields.mask_tensor(dims, DEV)
-    api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask)
+    o = api.Options()
+    o.workspace = fields.workspace(api.OP_STEP, dtype, dims, o)  # columns beyond the fused classes
+    api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask, opts=o)
     return u, data, w, out, mask
 
 

@@ -114,7 +114,8 @@ def test_vadv_full_size_residual():
 
 
 # ------------------------------------------------------------------ step
-STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (33, 17, 137), (20, 20, 161)]
+STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (9, 5, 2), (30, 70, 79), (33, 17, 137),
+              (20, 20, 161)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
@@ -122,7 +123,9 @@ STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (33, 17, 137)
     (api.IMPL_PLAIN, 0, 0),
     (api.IMPL_FUSED, 64, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 64, api.COLUMN_OUTBUF),
     (api.IMPL_FUSED, 32, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 16, api.COLUMN_OUTBUF),
-    (api.IMPL_AUTO, 0, 0)], ids=["plain", "t64reg", "t64out", "t32reg", "t16out", "auto"])
+    (api.IMPL_FUSED, 64, api.COLUMN_SPLIT), (api.IMPL_FUSED, 32, api.COLUMN_SPLIT),
+    (api.IMPL_FUSED, 16, api.COLUMN_SPLIT), (api.IMPL_AUTO, 0, 0)],
+    ids=["plain", "t64reg", "t64out", "t32reg", "t16out", "t64split", "t32split", "t16split", "auto"])
 @pytest.mark.parametrize("dims", STEP_CASES, ids=lambda d: "x".join(map(str, d)))
 def test_step(dims, impl, tile, col, dtype):
     ni, nj, nk = dims
