@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "grid points/s and HBM GB/s (% of peak) for fused hdiff+vadv step; adjoint/fwd ratio"
-KERNEL_SOURCES = ["common.hpp", "k_step.hpp", "k_step.hip", "k_step_inst.hip"]
+KERNEL_SOURCES = ["common.hpp", "k_step.hpp", "k_split.hpp", "k_step.hip", "k_step_inst.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fused_512x512x80_f64.json")
 
 
@@ -53,6 +53,28 @@ def adjoint_bytes(ni, nj, nk, es) -> int:
         nk * nj * ((ni + 63) // 64) * 16 + nk * (ni + nj)
 
 
+def copy_bandwidth(mib: int, reps: int) -> dict:
+    """A plain device-to-device copy of `mib` MiB (reads and writes that many
+    bytes): the achievable-bandwidth reference and the known-size kernel
+    the HBM byte counters are scaled by."""
+    import torch
+
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    return {"copy_mib": mib, "bytes_per_copy": 2 * n * 8, "s_per_copy": t, "gbs": round(2 * n * 8 / t / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +83,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-step", action="store_true", help="time the fused forward step only")
     ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only time a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
@@ -75,6 +99,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.copy_mib:
+        print(json.dumps(copy_bandwidth(args.copy_mib, args.reps)), flush=True)
+        return
     wl = inputs.STEP_512
     ni, nj, nk = wl.ni, wl.nj, wl.nk
     dims = (ni, nj, nk)
@@ -132,6 +159,15 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3 / reps
 
+    # ------------------------------------------------------------ autotuning
+    # the library's autotuner picks tile and column store for this size class
+    print("bench: autotuning the fused step and adjoint", file=sys.stderr, flush=True)
+    tuned = {}
+    for dt, name in ((api.F64, "f64"), (api.F32, "f32")):
+        api.stencil_autotune(dt, api.OP_STEP, dims, reps=3)
+        tuned[name] = api.stencil_tuning_lookup(dt, api.OP_STEP, dims)
+    api.stencil_autotune(api.F64, api.OP_STEP_ADJOINT, dims, reps=3)
+
     # ---------------------------------------------------------------- FP64 step
     print(f"bench: fused step {dims} fp64, {K} steps per graph, {args.reps} replays", file=sys.stderr,
           flush=True)
@@ -145,9 +181,12 @@ def main():
             tr = json.load(fh)
         if tr.get("kernel_hash") == kernel_hash():
             traffic = tr.get("bytes_per_launch")
+    ti, tj, col = tuned["f64"]
+    kname = (f"k_step_split<double, {ti}, {tj}, 40, 2, false>" if col == api.COLUMN_SPLIT
+             else f"k_step_fused<double, {ti}, {tj}, 80, 2, {col}>")
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": b64, "kernel": "k_step_fused<double,64,4,80,2,1>",
+            "algorithmic_bytes_per_launch": b64, "kernel": kname,
             "avg_launch_us": round(t_step * 1e6, 2)}
     out.update({
         "metric": METRIC, "value": round(npts * K / t_ev, 1), "unit": "grid points/s",
@@ -155,7 +194,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded U[0,1) u, U[-1,1] w, U[-0.1,0.1] data)",
         "config": {"workload": "fused hdiff+vadv step 512x512x80, halo 2, hipGraph of K steps",
-                   "ni": ni, "nj": nj, "nk": nk, "graph_steps": K, "wall_s_per_graph": round(t_wall, 6)},
+                   "ni": ni, "nj": nj, "nk": nk, "graph_steps": K, "wall_s_per_graph": round(t_wall, 6),
+                   "tuned_tile_f64": f"{tuned['f64'][0]}x{tuned['f64'][1]}", "column_store_f64": tuned["f64"][2],
+                   "tuned_tile_f32": f"{tuned['f32'][0]}x{tuned['f32'][1]}", "column_store_f32": tuned["f32"][2]},
         "roofline": roof,
     })
 
@@ -202,6 +243,12 @@ def main():
         torch.cuda.synchronize()
         out["python_call_us"] = round(host_call * 1e6, 2)
         del u_a, u_b, data, w, mask, xb, ub, db
+
+    # ------------------------------------------------------ achievable bandwidth
+    if not args.only_step:
+        cb = copy_bandwidth(1024, 10)
+        out["copy_reference"] = {"gbs": cb["gbs"], "what": "torch device copy of 1 GiB (read + write)",
+                                 "step_frac_of_copy": round(gbs / cb["gbs"], 4)}
 
     # -------------------------------------------------------------- CPU baseline
     if not args.no_cpu:

@@ -70,6 +70,24 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t off, f
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, 0);
 }
 
+// A per-lane byte offset that lies outside every window: a buffer store to
+// it is discarded and a load returns 0, which predicates a lane's access
+// without a branch.
+constexpr uint32_t kOffNone = 0xFFFFFFF0u;
+
+__device__ __forceinline__ void buf_st_u8(__amdgpu_buffer_rsrc_t r, uint32_t off, uint8_t v) {
+  __builtin_amdgcn_raw_buffer_store_b8(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_u16(__amdgpu_buffer_rsrc_t r, uint32_t off, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_u32(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t v) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_st_u64(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+
 // One field as seen by a kernel: the level-0 base, the level stride (bytes)
 // and the window (bytes) of one level.
 struct LevelView {
@@ -79,6 +97,16 @@ struct LevelView {
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t at(int k) const {
     return make_rsrc(base + (int64_t)k * level_bytes, window);
   }
+};
+
+// A level pointer that walks a field one level per step (either direction)
+// and can be held at a level: the uniform state of a marching kernel.
+struct LevelCursor {
+  const char* p;
+  int64_t step;
+  uint32_t window;
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc() const { return make_rsrc(p, window); }
+  __device__ __forceinline__ void advance(bool go) { p += go ? step : 0; }
 };
 
 // ------------------------------------------------------------ limiter

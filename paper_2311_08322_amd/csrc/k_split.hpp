@@ -25,12 +25,67 @@
 
 namespace gt4mi {
 
-template <typename T, int TI, int TJ, int NKH, int PD>
+// Branch-free recorder of one lane's limiter decisions (buffer stores; a
+// lane that stores nothing at a level uses an offset outside the window).
+struct MaskRec {
+  const char* base;
+  int64_t plane_xy, plane_ex, plane_ey, x_off, y_off, ex_off, ey_off;
+  uint32_t win_xy, win_ex, win_ey;
+  uint32_t off_row, off_ex, off_ey;
+  int shift;
+
+  template <typename T, int TI>
+  __device__ __forceinline__ void init(const StepArgs<T>& A, int lane_in_tile, int i0, int i, int j,
+                                       bool active) {
+    const int lane = lane_in_tile & 63;
+    base = reinterpret_cast<const char*>(A.mask);
+    plane_xy = (int64_t)A.nj * A.ml.words * 8;
+    plane_ex = A.nj;
+    plane_ey = A.ni;
+    x_off = A.ml.x_off;
+    y_off = A.ml.y_off;
+    ex_off = A.ml.ex_off;
+    ey_off = A.ml.ey_off;
+    win_xy = (uint32_t)plane_xy;
+    win_ex = (uint32_t)A.nj;
+    win_ey = (uint32_t)A.ni;
+    shift = (lane / TI) * TI;
+    off_row = ((lane % TI) == 0 && j < A.nj) ? (uint32_t)(j * A.ml.words * 8 + (i0 >> 3)) : kOffNone;
+    off_ex = (active && i == 0) ? (uint32_t)j : kOffNone;
+    off_ey = (active && j == 0) ? (uint32_t)i : kOffNone;
+  }
+
+  template <int TI>
+  __device__ __forceinline__ static void bits(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t b) {
+    if constexpr (TI == 64) buf_st_u64(r, off, b);
+    else if constexpr (TI == 32) buf_st_u32(r, off, (uint32_t)b);
+    else buf_st_u16(r, off, (uint16_t)b);
+  }
+
+  // every lane of the wave calls this (ballots); `act` is wave-uniform
+  template <int TI>
+  __device__ __forceinline__ void record(int k, bool act, bool active, bool kxr, bool kyr, bool kxl,
+                                         bool kyl) const {
+    const uint64_t bx = __ballot(active && kxr);
+    const uint64_t by = __ballot(active && kyr);
+    const uint32_t orow = act ? off_row : kOffNone;
+    bits<TI>(make_rsrc(base + x_off + (int64_t)k * plane_xy, win_xy), orow, bx >> shift);
+    bits<TI>(make_rsrc(base + y_off + (int64_t)k * plane_xy, win_xy), orow, by >> shift);
+    buf_st_u8(make_rsrc(base + ex_off + (int64_t)k * plane_ex, win_ex), act ? off_ex : kOffNone, kxl ? 1 : 0);
+    buf_st_u8(make_rsrc(base + ey_off + (int64_t)k * plane_ey, win_ey), act ? off_ey : kOffNone, kyl ? 1 : 0);
+  }
+};
+
+// The loop runs every step of the register class with no per-step branch
+// besides the barrier: a step past the half's last level reloads a clamped
+// level and leaves the factors unchanged (selects), so the prefetch stays
+// a fixed distance ahead and the load counters are exact.
+template <typename T, int TI, int TJ, int NKH, int PD, bool MASK>
 __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
   static_assert(NT == kWG, "tile must hold 256 columns");
-  __shared__ T su[2][2][NLD * NT];  // [half][level parity]
+  __shared__ T su[2][2][NLD * NT];  // [half][step parity]
   __shared__ T xch[2][2][NT];       // innermost (e, f) of each half and column
 
   const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // 0: top, 1: bottom
@@ -39,7 +94,7 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   t.init_lane(ltid, xcd_tile(blockIdx.x, gridDim.x), A.tiles_i, A.ni, A.nj, A.u_sj);
   const int nk = A.nk, m = nk / 2;
   const int nlev = half ? nk - m : m;  // levels this half eliminates
-  const int nsteps = nk - m;           // the larger of the two
+  const int k0 = half ? nk - 1 : 0, dir = half ? -1 : 1;
   constexpr uint32_t S = sizeof(T);
   const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, -2, -2, A.nj + 4);
   const LevelView vd = level_view(A.data, A.d_sj, A.d_sk, 0, 0, A.nj);
@@ -47,62 +102,79 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
   const uint32_t doff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.d_sj) * S;
   const uint32_t woff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.w_sj) * S;
-  const uint32_t ooff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.o_sj) * S;
+  const uint32_t ooff = t.active ? ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.o_sj) * S : kOffNone;
   const bool active = t.active;
-  MaskWriter mw;
-  if (A.mask) mw = MaskWriter::make<T, TI>(A, t.i0, t.i, t.j, active);
+  MaskRec mr;
+  if constexpr (MASK) mr.init<T, TI>(A, ltid, t.i0, t.i, t.j, active);
 
-  // step s works on level s (top) or nk-1-s (bottom); the w level that is
-  // new at step s is k+1 (top: c_k) or k (bottom: a_k)
+  // Load cursors walk this half's levels in step order and hold at its last
+  // level, so steps past it (odd nk, class padding) reload a valid level.
+  LevelCursor cur_u{vu.base + (int64_t)k0 * vu.level_bytes, dir * vu.level_bytes, vu.window};
+  LevelCursor cur_d{vd.base + (int64_t)k0 * vd.level_bytes, dir * vd.level_bytes, vd.window};
+  LevelCursor cur_w{vw.base + (int64_t)(half ? k0 : 1) * vw.level_bytes, dir * vw.level_bytes, vw.window};
   T pu[PD][NLD], pd[PD], pw[PD];
   auto issue = [&](int slot, int s) {
-    const int k = half ? nk - 1 - s : s;
-    const auto ru = vu.at(k);
+    const auto ru = cur_u.rsrc();
 #pragma unroll
     for (int q = 0; q < NLD; ++q) pu[slot][q] = buf_ld(ru, t.hoff[q], T());
-    pd[slot] = buf_ld(vd.at(k), doff, T());
-    pw[slot] = buf_ld(vw.at(half ? k : k + 1), woff, T());
+    pd[slot] = buf_ld(cur_d.rsrc(), doff, T());
+    pw[slot] = buf_ld(cur_w.rsrc(), woff, T());  // the w level new at this step
+    const bool go = s + 1 < nlev;
+    cur_u.advance(go);
+    cur_d.advance(go);
+    cur_w.advance(go);
   };
 #pragma unroll
-  for (int s = 0; s < PD; ++s)
-    if (s < nlev) issue(s, s);
+  for (int s = 0; s < PD; ++s) issue(s, s);
 
   T ev[NKH], fv[NKH];
   T wp = T(0), e = T(0), f = T(0);
   const T coeff = A.coeff;
   const T sn = half ? A.r4 : -A.r4;  // near coefficient per unit w: top a = -r/4 w, bottom c = +r/4 w
   const int cu = (t.tj + 2) * HI + (t.ti + 2);
+  T hq = T(0), dq = T(0), wq = T(0);  // the previous step's diffused value, data and new w
 
+  // Software pipeline: after the barrier of step s the diamond reads of s
+  // are issued first and the column elimination of step s-1 runs while
+  // they are in flight; then the diffusion of step s completes.
 #pragma unroll
-  for (int s = 0; s < NKH; ++s) {
-    if (s < nsteps) {
-      const bool act = s < nlev;
+  for (int s = 0; s <= NKH; ++s) {
+    __builtin_amdgcn_sched_barrier(0);
+    Diamond<T> dm;
+    T dk = T(0), wn = T(0);
+    if (s < NKH) {
       const int slot = s % PD;
       T* U = su[half][s & 1];
-      T dk = T(0), wn = T(0);
-      if (act) {
 #pragma unroll
-        for (int q = 0; q < NLD; ++q) U[ltid + q * NT] = pu[slot][q];
-        dk = pd[slot];
-        wn = pw[slot];
-        if (s + PD < nlev) issue(slot, s + PD);
-      }
+      for (int q = 0; q < NLD; ++q) U[ltid + q * NT] = pu[slot][q];
+      dk = pd[slot];
+      wn = pw[slot];
+      if (s + PD < NKH) issue(slot, s + PD);
       __syncthreads();
-      if (act) {
-        const int k = half ? nk - 1 - s : s;
-        bool kxr, kxl, kyr, kyl;
-        const T h = hdiff_diamond<T, HI>(U + cu, coeff, kxr, kxl, kyr, kyl);
-        if (A.mask) mw.record<TI>(k, active, kxr, kyr, kxl, kyl);
-        const T nr = (s > 0) ? sn * wp : T(0);                  // a_k (top, k >= 1) / c_k (bottom, k <= nk-2)
-        const T fr = (half == 0 || k > 0) ? -sn * wn : T(0);   // c_k (top) / a_k (bottom, k >= 1)
-        const T b = T(1) + absv(nr) + absv(fr);
-        const T inv = recip(b - nr * e);
-        e = fr * inv;
-        f = ((h + dk) - nr * f) * inv;
-        ev[s] = e;
-        fv[s] = f;
-        wp = wn;
-      }
+      dm = load_diamond<T, HI>(U + cu);
+    }
+    if (s > 0) {
+      const int sp = s - 1;
+      const bool act = sp < nlev;
+      const int k = k0 + dir * sp;
+      const T nr = (sp > 0) ? sn * wp : T(0);                 // a_k (top, k >= 1) / c_k (bottom, k <= nk-2)
+      const T fr = (half == 0 || k > 0) ? -sn * wq : T(0);   // c_k (top) / a_k (bottom, k >= 1)
+      const T b = T(1) + absv(nr) + absv(fr);
+      const T inv = recip(b - nr * e);
+      const T en = fr * inv;
+      const T fn = ((hq + dq) - nr * f) * inv;
+      e = act ? en : e;
+      f = act ? fn : f;
+      wp = act ? wq : wp;
+      ev[sp] = e;
+      fv[sp] = f;
+    }
+    if (s < NKH) {
+      bool kxr, kxl, kyr, kyl;
+      hq = hdiff_of(dm, coeff, kxr, kxl, kyr, kyl);
+      dq = dk;
+      wq = wn;
+      if constexpr (MASK) mr.record<TI>(min(max(k0 + dir * s, 0), nk - 1), s < nlev, active, kxr, kyr, kxl, kyl);
     }
   }
   // interface: the two innermost levels m-1 (top) and m (bottom)
@@ -117,10 +189,9 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   T x = half ? xm1 : xm;  // the value beyond this half's innermost level
 #pragma unroll
   for (int s = NKH - 1; s >= 0; --s) {
-    if (s < nlev) {
-      const int k = half ? nk - 1 - s : s;
+    if (s < nlev) {  // uniform; no loads follow, so the branch costs no waits
       x = fv[s] - ev[s] * x;
-      if (active) buf_st(vo.at(k), ooff, x);
+      buf_st(vo.at(k0 + dir * s), ooff, x);
     }
   }
 }
@@ -137,12 +208,15 @@ template <typename T, int TI, int TJ>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s) {
   const dim3 grid(A.ntiles), block(2 * TI * TJ);
   const int nkh = A.nk - A.nk / 2;
-#define GT4MI_SPLIT_CASE(N)                                                                 \
-  if constexpr (2 * N <= split_max_nk<T>()) {                                               \
-    if (nkh <= N) {                                                                         \
-      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD>), grid, block, 0, s, A);    \
-      return hipGetLastError();                                                             \
-    }                                                                                       \
+#define GT4MI_SPLIT_CASE(N)                                                                       \
+  if constexpr (2 * N <= split_max_nk<T>()) {                                                     \
+    if (nkh <= N) {                                                                               \
+      if (A.mask)                                                                                 \
+        hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, true>), grid, block, 0, s, A);  \
+      else                                                                                        \
+        hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, false>), grid, block, 0, s, A); \
+      return hipGetLastError();                                                                   \
+    }                                                                                             \
   }
   GT4MI_NKH_CLASSES(GT4MI_SPLIT_CASE)
 #undef GT4MI_SPLIT_CASE

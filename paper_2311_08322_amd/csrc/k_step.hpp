@@ -76,31 +76,61 @@ struct MaskWriter {
   }
 };
 
-// Horizontal diffusion of one point from the u-tile in LDS.  `c` points at
-// the lane's own u(i,j); HI is the tile's row pitch.  The five Laplacians
-// the point needs are formed from its 13-point diamond (no shared lap
-// stage, so one barrier per level suffices).  Returns out; the four flux
-// decisions go to kxr/kxl/kyr/kyl (right/left, x/y).
+// The 13-point diamond of u around a point (radius 2 in i and j): all the
+// values one output of the horizontal diffusion depends on.
+template <typename T>
+struct Diamond {
+  T u00, um1, up1, um2, up2, vm1, vp1, vm2, vp2, mm, mp, pm, pp;
+};
+
+// Read the diamond from the u-tile in LDS; `c` points at u(i,j), HI is the
+// tile's row pitch.
+template <typename T, int HI>
+__device__ __forceinline__ Diamond<T> load_diamond(const T* __restrict__ c) {
+  Diamond<T> d;
+  d.u00 = c[0];
+  d.um1 = c[-1];
+  d.up1 = c[1];
+  d.um2 = c[-2];
+  d.up2 = c[2];
+  d.vm1 = c[-HI];
+  d.vp1 = c[HI];
+  d.vm2 = c[-2 * HI];
+  d.vp2 = c[2 * HI];
+  d.mm = c[-HI - 1];
+  d.mp = c[-HI + 1];
+  d.pm = c[HI - 1];
+  d.pp = c[HI + 1];
+  return d;
+}
+
+// Horizontal diffusion of one point from its diamond.  The five Laplacians
+// the point needs are formed from the diamond (no shared lap stage, so one
+// barrier per level suffices).  Returns out; the four flux decisions go to
+// kxr/kxl/kyr/kyl (right/left, x/y).
+template <typename T>
+__device__ __forceinline__ T hdiff_of(const Diamond<T>& d, T coeff, bool& kxr, bool& kxl, bool& kyr,
+                                      bool& kyl) {
+  // lap = 4u - ((u[i-1] + u[i+1]) + (u[j-1] + u[j+1])) at (0,0), (+-1,0), (0,+-1)
+  const T L00 = T(4) * d.u00 - ((d.um1 + d.up1) + (d.vm1 + d.vp1));
+  const T Lp0 = T(4) * d.up1 - ((d.u00 + d.up2) + (d.mp + d.pp));
+  const T Lm0 = T(4) * d.um1 - ((d.um2 + d.u00) + (d.mm + d.pm));
+  const T L0p = T(4) * d.vp1 - ((d.pm + d.pp) + (d.u00 + d.vp2));
+  const T L0m = T(4) * d.vm1 - ((d.mm + d.mp) + (d.vm2 + d.u00));
+  const T fxr = Lp0 - L00, fxl = L00 - Lm0, fyr = L0p - L00, fyl = L00 - L0m;
+  kxr = flux_kept(fxr, d.up1 - d.u00);
+  kxl = flux_kept(fxl, d.u00 - d.um1);
+  kyr = flux_kept(fyr, d.vp1 - d.u00);
+  kyl = flux_kept(fyl, d.u00 - d.vm1);
+  const T Fxr = kxr ? fxr : T(0), Fxl = kxl ? fxl : T(0);
+  const T Fyr = kyr ? fyr : T(0), Fyl = kyl ? fyl : T(0);
+  return d.u00 - coeff * ((Fxr - Fxl) + (Fyr - Fyl));
+}
+
 template <typename T, int HI>
 __device__ __forceinline__ T hdiff_diamond(const T* __restrict__ c, T coeff, bool& kxr, bool& kxl,
                                            bool& kyr, bool& kyl) {
-  const T u00 = c[0], um1 = c[-1], up1 = c[1], um2 = c[-2], up2 = c[2];
-  const T vm1 = c[-HI], vp1 = c[HI], vm2 = c[-2 * HI], vp2 = c[2 * HI];
-  const T mm = c[-HI - 1], mp = c[-HI + 1], pm = c[HI - 1], pp = c[HI + 1];
-  // lap = 4u - ((u[i-1] + u[i+1]) + (u[j-1] + u[j+1])) at (0,0), (+-1,0), (0,+-1)
-  const T L00 = T(4) * u00 - ((um1 + up1) + (vm1 + vp1));
-  const T Lp0 = T(4) * up1 - ((u00 + up2) + (mp + pp));
-  const T Lm0 = T(4) * um1 - ((um2 + u00) + (mm + pm));
-  const T L0p = T(4) * vp1 - ((pm + pp) + (u00 + vp2));
-  const T L0m = T(4) * vm1 - ((mm + mp) + (vm2 + u00));
-  const T fxr = Lp0 - L00, fxl = L00 - Lm0, fyr = L0p - L00, fyl = L00 - L0m;
-  kxr = flux_kept(fxr, up1 - u00);
-  kxl = flux_kept(fxl, u00 - um1);
-  kyr = flux_kept(fyr, vp1 - u00);
-  kyl = flux_kept(fyl, u00 - vm1);
-  const T Fxr = kxr ? fxr : T(0), Fxl = kxl ? fxl : T(0);
-  const T Fyr = kyr ? fyr : T(0), Fyl = kyl ? fyl : T(0);
-  return u00 - coeff * ((Fxr - Fxl) + (Fyr - Fyl));
+  return hdiff_of(load_diamond<T, HI>(c), coeff, kxr, kxl, kyr, kyl);
 }
 
 // Level-invariant addressing of a TI x TJ tile: byte offsets of the
