@@ -36,6 +36,9 @@ def _units():
             for col in cols:
                 u.append(("k_step_inst.hip", f"step_{t}_{ti}_c{col}",
                           [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", f"-DGT4MI_COL={col}", *UNROLL]))
+        for adj in ("false", "true"):
+            u.append(("k_step_inst.hip", f"colsplit_{t}_{adj}",
+                      [f"-DGT4MI_T={t}", "-DGT4MI_COLSPLIT", f"-DGT4MI_ADJ={adj}", *UNROLL]))
         for ti in (64, 32, 16):
             u.append(("k_step_inst.hip", f"split_{t}_{ti}",
                       [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", *UNROLL]))

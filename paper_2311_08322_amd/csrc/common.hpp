@@ -99,6 +99,17 @@ struct LevelView {
   }
 };
 
+// Buffer view of a field whose pointer `p` is at domain point (0,0,0),
+// with the window starting at (di, dj) relative to it and `rows` rows long.
+template <typename T>
+__device__ __forceinline__ LevelView level_view(const T* p, int64_t sj, int64_t sk, int di, int dj, int rows) {
+  LevelView v;
+  v.base = reinterpret_cast<const char*>(p + di + (int64_t)dj * sj);
+  v.level_bytes = sk * (int64_t)sizeof(T);
+  v.window = (uint32_t)(sj * rows * (int64_t)sizeof(T));
+  return v;
+}
+
 // A level pointer that walks a field one level per step (either direction)
 // and can be held at a level: the uniform state of a marching kernel.
 struct LevelCursor {

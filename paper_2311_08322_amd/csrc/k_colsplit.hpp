@@ -1,0 +1,125 @@
+// k_colsplit.hpp -- the column solves alone (vertical advection and its
+// adjoint), each column eliminated from both ends by two lanes.
+//
+// Forward:  T x = u + data.  Adjoint:  T^T lambda = x_bar.
+// T^T is tridiagonal with sub-diagonal c_{k-1}, diagonal b_k and
+// super-diagonal a_{k+1}; in terms of w the near/far coefficients of the two
+// sweeps (see k_split.hpp) are those of T with the sign flipped:
+//   top, level k:    near = c_{k-1} = +r/4 w_k,      far = a_{k+1} = -r/4 w_{k+1}
+//   bottom, level k: near = a_{k+1} = -r/4 w_{k+1},  far = c_{k-1} = +r/4 w_k
+// while the diagonal b_k = 1 + |a_k| + |c_k| = 1 + |near| + |far| is the same.
+// So both solves are one kernel: a sign and the right-hand side differ.
+#pragma once
+
+#include "k_step.hpp"
+
+namespace gt4mi {
+
+template <typename T, int NKH, int PD, bool ADJ>
+__global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
+  constexpr int NT = kWG;
+  __shared__ T xch[2][2][NT];
+  const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // 0: top, 1: bottom
+  const int ltid = threadIdx.x - half * NT;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int bi = tile % A.tiles_i, bj = tile / A.tiles_i;
+  const int i = bi * 64 + (ltid & 63), j = bj * 4 + (ltid >> 6);
+  const bool active = (i < A.ni) && (j < A.nj);
+  const int ic = min(i, A.ni - 1), jc = min(j, A.nj - 1);
+  const int nk = A.nk, m = nk / 2;
+  const int nlev = half ? nk - m : m;
+  const int k0 = half ? nk - 1 : 0, dir = half ? -1 : 1;
+  constexpr uint32_t S = sizeof(T);
+  // forward: u (rhs part 1), data (part 2); adjoint: u holds x_bar, data unused
+  const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, 0, 0, A.nj);
+  const LevelView vd = level_view(A.data, A.d_sj, A.d_sk, 0, 0, A.nj);
+  const LevelView vw = level_view(A.w, A.w_sj, A.w_sk, 0, 0, A.nj);
+  const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
+  const uint32_t uoff = ((uint32_t)ic + (uint32_t)jc * (uint32_t)A.u_sj) * S;
+  const uint32_t doff = ((uint32_t)ic + (uint32_t)jc * (uint32_t)A.d_sj) * S;
+  const uint32_t woff = ((uint32_t)ic + (uint32_t)jc * (uint32_t)A.w_sj) * S;
+  const uint32_t ooff = active ? ((uint32_t)ic + (uint32_t)jc * (uint32_t)A.o_sj) * S : kOffNone;
+
+  LevelCursor cur_u{vu.base + (int64_t)k0 * vu.level_bytes, dir * vu.level_bytes, vu.window};
+  LevelCursor cur_d{vd.base + (int64_t)k0 * vd.level_bytes, dir * vd.level_bytes, vd.window};
+  LevelCursor cur_w{vw.base + (int64_t)(half ? k0 : 1) * vw.level_bytes, dir * vw.level_bytes, vw.window};
+  T pr[PD], pw[PD];
+  auto issue = [&](int slot, int s) {
+    T r = buf_ld(cur_u.rsrc(), uoff, T());
+    if constexpr (!ADJ) r += buf_ld(cur_d.rsrc(), doff, T());
+    pr[slot] = r;
+    pw[slot] = buf_ld(cur_w.rsrc(), woff, T());
+    const bool go = s + 1 < nlev;
+    cur_u.advance(go);
+    if constexpr (!ADJ) cur_d.advance(go);
+    cur_w.advance(go);
+  };
+#pragma unroll
+  for (int s = 0; s < PD; ++s) issue(s, s);
+
+  T ev[NKH], fv[NKH];
+  T wp = T(0), e = T(0), f = T(0);
+  const T sn = (half ? A.r4 : -A.r4) * (ADJ ? T(-1) : T(1));
+#pragma unroll
+  for (int s = 0; s < NKH; ++s) {
+    __builtin_amdgcn_sched_barrier(0);
+    const int slot = s % PD;
+    const T rhs = pr[slot], wn = pw[slot];
+    if (s + PD < NKH) issue(slot, s + PD);
+    const bool act = s < nlev;
+    const int k = k0 + dir * s;
+    const T nr = (s > 0) ? sn * wp : T(0);
+    const T fr = (half == 0 || k > 0) ? -sn * wn : T(0);
+    const T b = T(1) + absv(nr) + absv(fr);
+    const T inv = recip(b - nr * e);
+    const T en = fr * inv;
+    const T fn = (rhs - nr * f) * inv;
+    e = act ? en : e;
+    f = act ? fn : f;
+    wp = act ? wn : wp;
+    ev[s] = e;
+    fv[s] = f;
+  }
+  xch[half][0][ltid] = e;
+  xch[half][1][ltid] = f;
+  __syncthreads();
+  const T eo = xch[1 - half][0][ltid], fo = xch[1 - half][1][ltid];
+  const T et = half ? eo : e, ft = half ? fo : f;
+  const T eb = half ? e : eo, fb = half ? f : fo;
+  const T xm = (fb - eb * ft) * recip(T(1) - eb * et);
+  const T xm1 = ft - et * xm;
+  T x = half ? xm1 : xm;
+#pragma unroll
+  for (int s = NKH - 1; s >= 0; --s) {
+    if (s < nlev) {
+      x = fv[s] - ev[s] * x;
+      buf_st(vo.at(k0 + dir * s), ooff, x);
+    }
+  }
+}
+
+template <typename T>
+constexpr int column_split_max_nk() {
+  return sizeof(T) == 8 ? 96 : 160;  // both halves' factors in <= 256 VGPRs
+}
+
+template <typename T, bool ADJ>
+hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s) {
+  A.tiles_i = (A.ni + 63) / 64;
+  A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
+  const dim3 grid(A.ntiles), block(2 * kWG);
+  const int nkh = A.nk - A.nk / 2;
+#define GT4MI_COLSPLIT_CASE(N)                                                              \
+  if constexpr (2 * N <= column_split_max_nk<T>()) {                                       \
+    if (nkh <= N) {                                                                         \
+      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_PD, ADJ>), grid, block, 0, s, A);     \
+      return hipGetLastError();                                                             \
+    }                                                                                       \
+  }
+  GT4MI_COLSPLIT_CASE(8) GT4MI_COLSPLIT_CASE(16) GT4MI_COLSPLIT_CASE(24) GT4MI_COLSPLIT_CASE(32)
+  GT4MI_COLSPLIT_CASE(40) GT4MI_COLSPLIT_CASE(48) GT4MI_COLSPLIT_CASE(64) GT4MI_COLSPLIT_CASE(80)
+#undef GT4MI_COLSPLIT_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gt4mi

@@ -34,6 +34,7 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
 
 template <typename T>
 hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s) {
+  if (A.nk <= column_split_limit(sizeof(T))) return launch_column_split_classes<T, false>(A, s);
   A.tiles_i = (A.ni + 63) / 64;
   A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
   if constexpr (sizeof(T) == 4) {

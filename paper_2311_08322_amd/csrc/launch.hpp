@@ -20,6 +20,11 @@ template <typename T, int COL>
 hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int TI, int TJ>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
+// two-ended column solve: ADJ = false, out = T^{-1}(u + data);
+// ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 96 (FP64) / 160 (FP32)
+template <typename T, bool ADJ>
+hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s);
+constexpr int column_split_limit(int elem_bytes) { return elem_bytes == 8 ? 96 : 160; }
 template <typename T>
 hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s);
 template <typename T>
