@@ -98,7 +98,9 @@ typedef enum {
   STENCIL_COLUMN_OUTBUF = 2,    /* one lane per column, c' in VGPRs, d' staged in out */
   STENCIL_COLUMN_SPLIT = 3      /* two lanes per column eliminating from both ends,
                                    each holding half the factors in VGPRs (fused
-                                   step: nk <= 80 in FP64, <= 160 in FP32) */
+                                   step: nk <= 160 in FP32; in FP64 nk <= 80, and
+                                   nk <= 144 with f staged in out; longer columns
+                                   take the one-ended solve) */
 } stencil_column_store;
 
 /* Optional per-call options; pass NULL for defaults. */
@@ -192,6 +194,18 @@ int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
                          double dt_dz, const stencil_options* opts, hipStream_t stream);
 
 /* ------------------------------------------------------------- batched */
+/* Many independent fields of uneven sizes in one persistent launch (each
+ * field is its own stencil call in the sense of Sec. 2.2; the batch only
+ * shares the launch).  Every item obeys the rules of the single-field call
+ * it stands for, and additionally no output of one item may overlap any
+ * buffer of another (all items run concurrently): STENCIL_E_ALIAS.
+ * Limits: n <= 1024 items, nk <= 144 per item (STENCIL_E_UNSUPPORTED), the
+ * fused kernels only (impl PLAIN: STENCIL_E_UNSUPPORTED).  Items with an
+ * empty domain are skipped (their outputs untouched), except that an
+ * adjoint item with nk > 0 and an empty horizontal domain zeroes u_bar as
+ * the single-field adjoint does.  The tile is opts->tile_i, else the tuning
+ * table's entry for the batch's largest field. */
+
 /* One field of a batch: forward step out = step(u, data, w) on `domain`. */
 typedef struct {
   stencil_field u, data, w, out;
@@ -200,7 +214,7 @@ typedef struct {
   void* mask; /* NULL or stencil_mask_bytes(domain) bytes */
 } stencil_batch_item;
 
-/* One field of an adjoint batch. */
+/* One field of an adjoint batch (arguments of stencil_step_adjoint). */
 typedef struct {
   stencil_field x_bar, w, u_bar, data_bar; /* data_bar.data may be NULL */
   int64_t domain[3];
@@ -208,18 +222,28 @@ typedef struct {
   const void* mask;
 } stencil_batch_adjoint_item;
 
-/* Workspace for a batch: the work list and queue counter (and, for the
- * adjoint, the column adjoints of items without data_bar). */
+/* Device workspace of a batch (0 for n <= 0, an invalid dtype, or a batch
+ * with no work): the work list (a header, per-field prefix sums of work
+ * items and the argument blocks of the fields, rewritten by every call) and,
+ * for the adjoint, lambda = T^{-T} x_bar of every item without data_bar. */
 size_t stencil_batch_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_item* items);
 size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
                                              const stencil_batch_adjoint_item* items);
 
-/* All n steps in one persistent launch: workgroups pull (field, tile) work
- * items, longest first, from a device queue in `ws`. */
+/* All n steps in one persistent launch.  The call sorts the items longest
+ * column first, writes the work list into `ws` with small copy kernels on
+ * `stream` (stream-ordered, so the call can be captured into a graph), and
+ * launches one kernel whose workgroups pull (field, tile) work items from a
+ * device counter in `ws` until none are left.  ws: device memory, 256-byte
+ * aligned, at least stencil_batch_workspace_bytes(...) bytes, not
+ * overlapping any field (STENCIL_E_WORKSPACE / STENCIL_E_ALIAS); two calls
+ * that may run at the same time need distinct workspaces. */
 int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
                          size_t ws_bytes, const stencil_options* opts, hipStream_t stream);
-/* The adjoints of a batch: one persistent launch for the column adjoints,
- * one for the horizontal gathers. */
+/* The adjoints of a batch: one persistent launch for the column adjoints
+ * (work items: field, 64x4 column tile), one for the horizontal gathers
+ * (work items: field, tile of the padded domain, block of levels).  ws as
+ * for the forward, sized by stencil_batch_adjoint_workspace_bytes. */
 int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
                                  const stencil_batch_adjoint_item* items, void* ws,
                                  size_t ws_bytes, const stencil_options* opts,

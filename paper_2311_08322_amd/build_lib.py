@@ -25,7 +25,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function",
 ]
-UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000"]
+UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000", "-mllvm", "-unroll-max-upperbound=1000"]
 
 
 def _units():
@@ -46,6 +46,8 @@ def _units():
             u.append(("k_step_inst.hip", f"vadv_{t}_c{col}",
                       [f"-DGT4MI_T={t}", "-DGT4MI_VADV", f"-DGT4MI_COL={col}", *UNROLL]))
             u.append(("k_vadj_inst.hip", f"vadj_{t}_c{col}", [f"-DGT4MI_T={t}", f"-DGT4MI_COL={col}", *UNROLL]))
+        u.append(("k_batched.hip", f"batched_{t}",
+                  [f"-DGT4MI_T={t}", *(["-DGT4MI_UPLOAD"] if t == "float" else []), *UNROLL]))
     for src in ("k_adjoint.hip", "k_hdiff.hip", "k_plain.hip", "k_step.hip", "api.cpp", "tune.cpp",
                 "graph.cpp", "batched.cpp"):
         u.append((src, os.path.splitext(src)[0], []))

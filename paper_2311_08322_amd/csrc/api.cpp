@@ -145,7 +145,7 @@ ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, co
   r.tile_i = (o && o->tile_i) ? o->tile_i : ti;
   r.column_store = (o && o->column_store) ? o->column_store : col;
   if (r.column_store == STENCIL_COLUMN_AUTO) {
-    if (op == STENCIL_OP_STEP && dom[2] <= (dt == STENCIL_F64 ? 80 : 160))
+    if (op == STENCIL_OP_STEP && dom[2] <= split_step_limit((int)esize(dt)))
       r.column_store = STENCIL_COLUMN_SPLIT;
     else
       r.column_store = (dt == STENCIL_F64 && dom[2] > 96) ? STENCIL_COLUMN_OUTBUF : STENCIL_COLUMN_REGISTERS;
@@ -205,17 +205,6 @@ size_t adj_ws_bytes(size_t es, const int64_t* dom, bool need_lam, bool plain) {
 
 // ------------------------------------------------------------------ arg blocks
 template <typename T>
-const T* at_origin(const stencil_field* f) {
-  return static_cast<const T*>(f->data) + f->origin[0] + f->origin[1] * f->stride[1] +
-         f->origin[2] * f->stride[2];
-}
-template <typename T>
-T* at_origin_mut(stencil_field* f) {
-  return static_cast<T*>(f->data) + f->origin[0] + f->origin[1] * f->stride[1] +
-         f->origin[2] * f->stride[2];
-}
-
-template <typename T>
 StepArgs<T> step_args(const stencil_field* u, const stencil_field* data, const stencil_field* w,
                       stencil_field* out, const int64_t* dom, double coeff, double dt_dz,
                       void* mask) {
@@ -261,6 +250,11 @@ AdjArgs<T> adj_args(const stencil_field* xbar, const stencil_field* w, T* lam, i
   A.r4 = (T)(0.25 * dt_dz);
   return A;
 }
+
+template AdjArgs<float> adj_args<float>(const stencil_field*, const stencil_field*, float*, int64_t, int64_t,
+                                      stencil_field*, const int64_t*, double, double, const void*);
+template AdjArgs<double> adj_args<double>(const stencil_field*, const stencil_field*, double*, int64_t, int64_t,
+                                        stencil_field*, const int64_t*, double, double, const void*);
 
 // ------------------------------------------------------------------ dispatch
 template <typename T>
@@ -367,12 +361,6 @@ size_t stencil_workspace_bytes(int op, stencil_dtype dtype, const int64_t domain
       return 0;
   }
 }
-
-#define TRY(x)            \
-  do {                    \
-    int rc_ = (x);        \
-    if (rc_) return rc_;  \
-  } while (0)
 
 static int need_plain_ws(const ResolvedOpts& r, size_t need) {
   if (need == 0) return STENCIL_OK;

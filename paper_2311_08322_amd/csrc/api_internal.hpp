@@ -6,6 +6,13 @@
 #include <stdint.h>
 
 #include "../../include/stencil.h"
+#include "common.hpp"
+
+#define TRY(x)            \
+  do {                    \
+    int rc_ = (x);        \
+    if (rc_) return rc_;  \
+  } while (0)
 
 namespace gt4mi {
 
@@ -38,6 +45,25 @@ struct ResolvedOpts {
 };
 ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, const int64_t* dom);
 size_t plain_ws_bytes(size_t es, const int64_t* dom);
+
+// kernel argument blocks from field descriptors (pointers at the domain origin)
+template <typename T>
+inline const T* at_origin(const stencil_field* f) {
+  return static_cast<const T*>(f->data) + f->origin[0] + f->origin[1] * f->stride[1] +
+         f->origin[2] * f->stride[2];
+}
+template <typename T>
+inline T* at_origin_mut(stencil_field* f) {
+  return static_cast<T*>(f->data) + f->origin[0] + f->origin[1] * f->stride[1] +
+         f->origin[2] * f->stride[2];
+}
+template <typename T>
+StepArgs<T> step_args(const stencil_field* u, const stencil_field* data, const stencil_field* w,
+                      stencil_field* out, const int64_t* dom, double coeff, double dt_dz, void* mask);
+template <typename T>
+AdjArgs<T> adj_args(const stencil_field* xbar, const stencil_field* w, T* lam, int64_t l_sj,
+                    int64_t l_sk, stencil_field* ubar, const int64_t* dom, double coeff,
+                    double dt_dz, const void* mask);
 
 // tuning table (tune.cpp): tile and column store for (dtype, op, size class)
 void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* tile_i, int32_t* tile_j,

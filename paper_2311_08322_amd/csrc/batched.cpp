@@ -1,22 +1,390 @@
-// batched.cpp -- placeholder entry points of the batched launch.
+// batched.cpp -- the C ABI of the persistent batched launches: per-item
+// validation (the single-field rules plus no output of one field touching
+// any buffer of another, since all fields run concurrently), the work list
+// (fields sorted longest column first, prefix sums of their work items) and
+// its upload into the caller's workspace, then one persistent launch per
+// kernel.  Workspace layout, each part 256-byte aligned:
+//   forward:  [header + prefix][argument blocks]
+//   adjoint:  [column table][horizontal table][lambda of items without data_bar]
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "../../include/stencil.h"
 #include "api_internal.hpp"
+#include "launch.hpp"
+
+namespace gt4mi {
+namespace {
+
+constexpr int kMaxBatch = 1024;  // fields per call (keeps the O(n^2) alias check cheap)
+constexpr int kWsAlign = 256;
+
+int64_t r256(int64_t b) { return MaskLayout::round256(b); }
+
+// bytes of one table: header, prefix[n + 1], kper[n], then n argument blocks
+int64_t table_head_bytes(int n) { return r256((int64_t)sizeof(BatchHeader) + 4 * (2 * (int64_t)n + 1)); }
+int64_t table_bytes(int n, size_t arg_bytes) { return table_head_bytes(n) + r256((int64_t)n * (int64_t)arg_bytes); }
+
+size_t arg_bytes(stencil_dtype dt, bool adj) {
+  if (dt == STENCIL_F64) return adj ? sizeof(AdjArgs<double>) : sizeof(StepArgs<double>);
+  return adj ? sizeof(AdjArgs<float>) : sizeof(StepArgs<float>);
+}
+
+int64_t lam_bytes(size_t es, const int64_t* dom) { return r256(dom[0] * dom[1] * dom[2] * (int64_t)es); }
+
+Span mask_span(const void* mask, const int64_t* dom) {
+  const uintptr_t p = reinterpret_cast<uintptr_t>(mask);
+  return Span{p, mask ? p + stencil_mask_bytes(dom) : p};
+}
+
+// The tile of a batched launch: the caller's, else the tuning table's entry
+// for the batch's largest field (one persistent kernel runs one tile shape).
+template <typename Item>
+int tile_i_of(const stencil_options* o, stencil_dtype dt, int op, int n, const Item* it) {
+  if (o && o->tile_i) return o->tile_i;
+  int best = -1;
+  int64_t most = -1;
+  for (int a = 0; a < n; ++a) {
+    const int64_t p = it[a].domain[0] * it[a].domain[1] * it[a].domain[2];
+    if (p > most) most = p, best = a;
+  }
+  if (best < 0) return 64;
+  int32_t ti = 64, tj = 4, col = 0;
+  tuning_get(dt, op, it[best].domain, &ti, &tj, &col);
+  return (ti == 16 || ti == 32) ? ti : 64;
+}
+
+int check_batch_args(stencil_dtype dtype, int n, const void* items, const stencil_options* opts) {
+  TRY(check_dtype(dtype));
+  if (n < 0 || n > kMaxBatch) return fail(STENCIL_E_ARG, "batch of %d fields (0..%d)", n, kMaxBatch);
+  if (n > 0 && !items) return fail(STENCIL_E_NULL, "items is NULL");
+  TRY(check_opts(opts));
+  if (opts && opts->impl == STENCIL_IMPL_PLAIN)
+    return fail(STENCIL_E_UNSUPPORTED, "the batched launch runs the fused kernels only");
+  return STENCIL_OK;
+}
+
+// The spans one item reads and writes.
+struct ItemSpans {
+  std::vector<Span> rd, wr;
+};
+
+// Writes of one item against every buffer of every other item.
+int check_cross_alias(const std::vector<ItemSpans>& sp) {
+  const size_t n = sp.size();
+  for (size_t a = 0; a < n; ++a)
+    for (const Span& w : sp[a].wr) {
+      if (w.lo == w.hi) continue;
+      for (size_t b = 0; b < n; ++b) {
+        if (b == a) continue;
+        for (const Span& o : sp[b].wr)
+          if (overlap(w, o)) return fail(STENCIL_E_ALIAS, "an output of item %zu overlaps an output of item %zu", a, b);
+        for (const Span& o : sp[b].rd)
+          if (overlap(w, o)) return fail(STENCIL_E_ALIAS, "an output of item %zu overlaps an input of item %zu", a, b);
+      }
+    }
+  return STENCIL_OK;
+}
+
+int check_workspace(void* ws, size_t ws_bytes, size_t need, const std::vector<ItemSpans>& sp) {
+  if (need == 0) return STENCIL_OK;
+  if (!ws) return fail(STENCIL_E_WORKSPACE, "the batch needs %zu bytes of workspace (ws is NULL)", need);
+  if (ws_bytes < need) return fail(STENCIL_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) % kWsAlign)
+    return fail(STENCIL_E_WORKSPACE, "workspace must be %d-byte aligned", kWsAlign);
+  const Span s{reinterpret_cast<uintptr_t>(ws), reinterpret_cast<uintptr_t>(ws) + need};
+  for (size_t a = 0; a < sp.size(); ++a) {
+    for (const Span& o : sp[a].wr)
+      if (overlap(s, o)) return fail(STENCIL_E_ALIAS, "the workspace overlaps an output of item %zu", a);
+    for (const Span& o : sp[a].rd)
+      if (overlap(s, o)) return fail(STENCIL_E_ALIAS, "the workspace overlaps an input of item %zu", a);
+  }
+  return STENCIL_OK;
+}
+
+int check_item_nk(const int64_t* dom) {
+  if (dom[2] > kMaxBatchedNk)
+    return fail(STENCIL_E_UNSUPPORTED, "nk = %lld exceeds the batched column limit %d", (long long)dom[2],
+                kMaxBatchedNk);
+  return STENCIL_OK;
+}
+
+// Per-item validation of a forward batch; fills the spans.
+int check_forward_items(stencil_dtype dtype, int n, const stencil_batch_item* it, std::vector<ItemSpans>& sp) {
+  const size_t es = esize(dtype);
+  sp.resize(n);
+  for (int a = 0; a < n; ++a) {
+    const stencil_batch_item& x = it[a];
+    const int64_t* dom = x.domain;
+    int rc = check_domain(dom);
+    if (!rc) rc = check_field("u", &x.u, dom, ROLE_HALO, es);
+    if (!rc) rc = check_field("data", &x.data, dom, ROLE_INTERIOR, es);
+    if (!rc) rc = check_field("w", &x.w, dom, ROLE_STAGGERED, es);
+    if (!rc) rc = check_field("out", &x.out, dom, ROLE_INTERIOR, es);
+    if (!rc) rc = check_item_nk(dom);
+    ItemSpans& s = sp[a];
+    if (!rc) {
+      s.rd = {span_of(&x.u, es), span_of(&x.data, es), span_of(&x.w, es)};
+      s.wr = {span_of(&x.out, es), mask_span(x.mask, dom)};
+      for (const Span& w : s.wr)
+        for (const Span& r : s.rd)
+          if (!rc && overlap(w, r)) rc = fail(STENCIL_E_ALIAS, "an output of the item overlaps one of its inputs");
+      if (!rc && overlap(s.wr[0], s.wr[1])) rc = fail(STENCIL_E_ALIAS, "mask overlaps out");
+    }
+    if (rc) return fail(rc, "item %d: %s", a, stencil_last_error());
+  }
+  return check_cross_alias(sp);
+}
+
+int check_adjoint_items(stencil_dtype dtype, int n, const stencil_batch_adjoint_item* it, std::vector<ItemSpans>& sp) {
+  const size_t es = esize(dtype);
+  sp.resize(n);
+  for (int a = 0; a < n; ++a) {
+    const stencil_batch_adjoint_item& x = it[a];
+    const int64_t* dom = x.domain;
+    int rc = check_domain(dom);
+    if (!rc) rc = check_field("x_bar", &x.x_bar, dom, ROLE_INTERIOR, es);
+    if (!rc) rc = check_field("w", &x.w, dom, ROLE_STAGGERED, es);
+    if (!rc) rc = check_field("u_bar", &x.u_bar, dom, ROLE_HALO, es);
+    if (!rc && x.data_bar.data) rc = check_field("data_bar", &x.data_bar, dom, ROLE_INTERIOR, es);
+    if (!rc) rc = check_item_nk(dom);
+    if (!rc && !x.mask && dom[2] > 0 && !domain_empty(dom)) rc = fail(STENCIL_E_NULL, "mask is NULL");
+    ItemSpans& s = sp[a];
+    if (!rc) {
+      s.rd = {span_of(&x.x_bar, es), span_of(&x.w, es), mask_span(x.mask, dom)};
+      s.wr = {span_of(&x.u_bar, es)};
+      if (x.data_bar.data) s.wr.push_back(span_of(&x.data_bar, es));
+      for (const Span& w : s.wr)
+        for (const Span& r : s.rd)
+          if (!rc && overlap(w, r)) rc = fail(STENCIL_E_ALIAS, "an output of the item overlaps one of its inputs");
+      if (!rc && s.wr.size() == 2 && overlap(s.wr[0], s.wr[1])) rc = fail(STENCIL_E_ALIAS, "data_bar overlaps u_bar");
+    }
+    if (rc) return fail(rc, "item %d: %s", a, stencil_last_error());
+  }
+  return check_cross_alias(sp);
+}
+
+// Items with work, longest column first (ties by index, so the order is
+// deterministic).
+template <typename Item>
+std::vector<int> lpt_order(int n, const Item* it, bool (*has_work)(const int64_t*)) {
+  std::vector<int> ord;
+  for (int a = 0; a < n; ++a)
+    if (has_work(it[a].domain)) ord.push_back(a);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return it[x].domain[2] > it[y].domain[2]; });
+  return ord;
+}
+
+bool interior_work(const int64_t* d) { return !domain_empty(d); }
+bool halo_work(const int64_t* d) { return d[2] > 0; }
+
+// Writes one table (header, prefix, kper, argument blocks) into blob at off.
+template <typename Args>
+int32_t write_table(std::vector<uint8_t>& blob, size_t off, const std::vector<Args>& args,
+                    const std::vector<int32_t>& items, const std::vector<int32_t>& kper) {
+  const int n = (int)args.size();
+  BatchHeader h;
+  memset(&h, 0, sizeof h);
+  h.n = n;
+  std::vector<int32_t> prefix(n + 1, 0);
+  for (int e = 0; e < n; ++e) prefix[e + 1] = prefix[e] + items[e];
+  h.total = prefix[n];
+  uint8_t* p = blob.data() + off;
+  memcpy(p, &h, sizeof h);
+  memcpy(p + sizeof h, prefix.data(), 4 * (n + 1));
+  if (!kper.empty()) memcpy(p + sizeof h + 4 * (n + 1), kper.data(), 4 * n);
+  if (n) memcpy(p + table_head_bytes(n), args.data(), n * sizeof(Args));
+  return h.total;
+}
+
+// ---------------------------------------------------------------- forward
+template <typename T>
+int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, hipStream_t s) {
+  const int tile_j = kWG / tile_i;
+  const std::vector<int> ord = lpt_order(n, it, interior_work);
+  if (ord.empty()) return ok();
+  const int m = (int)ord.size();
+  std::vector<StepArgs<T>> args(m);
+  std::vector<int32_t> items(m);
+  bool any_mask = false;
+  int64_t total = 0;
+  for (int e = 0; e < m; ++e) {
+    const stencil_batch_item& x = it[ord[e]];
+    StepArgs<T> A = step_args<T>(&x.u, &x.data, &x.w, const_cast<stencil_field*>(&x.out), x.domain, x.coeff,
+                                 x.dt_dz, x.mask);
+    A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+    A.ntiles = A.tiles_i * ((A.nj + tile_j - 1) / tile_j);
+    args[e] = A;
+    items[e] = A.ntiles;
+    total += A.ntiles;
+    any_mask |= x.mask != nullptr;
+  }
+  if (total > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch of %lld tiles is too large", (long long)total);
+  std::vector<uint8_t> blob((size_t)table_bytes(m, sizeof(StepArgs<T>)), 0);
+  write_table(blob, 0, args, items, {});
+  TRY(hip_status(launch_upload(ws, blob.data(), blob.size(), s), "batched table upload"));
+  BatchHeader* h = static_cast<BatchHeader*>(ws);
+  const auto* ent = reinterpret_cast<const StepArgs<T>*>(static_cast<char*>(ws) + table_head_bytes(m));
+  return hip_status(launch_step_batched<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched)");
+}
+
+// ---------------------------------------------------------------- adjoint
+size_t adjoint_ws(stencil_dtype dt, int n, const stencil_batch_adjoint_item* it) {
+  int mv = 0, mh = 0;
+  int64_t lam = 0;
+  for (int a = 0; a < n; ++a) {
+    const int64_t* d = it[a].domain;
+    if (interior_work(d)) {
+      ++mv;
+      if (!it[a].data_bar.data) lam += lam_bytes(esize(dt), d);
+    }
+    if (halo_work(d)) ++mh;
+  }
+  if (mh == 0) return 0;
+  return (size_t)(table_bytes(mv, arg_bytes(dt, false)) + table_bytes(mh, arg_bytes(dt, true)) + lam);
+}
+
+template <typename T>
+int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* ws, int tile_i, hipStream_t s) {
+  const int tile_j = kWG / tile_i;
+  const std::vector<int> vord = lpt_order(n, it, interior_work);
+  const std::vector<int> hord = lpt_order(n, it, halo_work);
+  if (hord.empty()) return ok();
+  const int mv = (int)vord.size(), mh = (int)hord.size();
+  char* base = static_cast<char*>(ws);
+  const int64_t vbytes = table_bytes(mv, sizeof(StepArgs<T>));
+  const int64_t hbytes = table_bytes(mh, sizeof(AdjArgs<T>));
+
+  // lambda of each item: data_bar, else a workspace slice (dense, ni x nj x nk)
+  std::vector<T*> lam(n, nullptr);
+  std::vector<int64_t> lsj(n, 0), lsk(n, 0);
+  int64_t lam_off = vbytes + hbytes;
+  for (int a = 0; a < n; ++a) {
+    const stencil_batch_adjoint_item& x = it[a];
+    const int64_t* d = x.domain;
+    if (!interior_work(d)) continue;
+    if (x.data_bar.data) {
+      lam[a] = at_origin_mut<T>(const_cast<stencil_field*>(&x.data_bar));
+      lsj[a] = x.data_bar.stride[1];
+      lsk[a] = x.data_bar.stride[2];
+    } else {
+      lam[a] = reinterpret_cast<T*>(base + lam_off);
+      lsj[a] = d[0];
+      lsk[a] = d[0] * d[1];
+      lam_off += lam_bytes(sizeof(T), d);
+    }
+  }
+
+  // column adjoints: 64 x 4 column tiles
+  std::vector<StepArgs<T>> vargs(mv);
+  std::vector<int32_t> vitems(mv);
+  int64_t vtotal = 0;
+  for (int e = 0; e < mv; ++e) {
+    const int a = vord[e];
+    const stencil_batch_adjoint_item& x = it[a];
+    StepArgs<T> C = step_args<T>(&x.x_bar, nullptr, &x.w, nullptr, x.domain, 0.0, x.dt_dz, nullptr);
+    C.out = lam[a];
+    C.o_sj = lsj[a];
+    C.o_sk = lsk[a];
+    C.tiles_i = (C.ni + 63) / 64;
+    C.ntiles = C.tiles_i * ((C.nj + 3) / 4);
+    vargs[e] = C;
+    vitems[e] = C.ntiles;
+    vtotal += C.ntiles;
+  }
+
+  // horizontal gathers: tiles over the padded domain, in blocks of levels
+  std::vector<AdjArgs<T>> hargs(mh);
+  for (int e = 0; e < mh; ++e) {
+    const int a = hord[e];
+    const stencil_batch_adjoint_item& x = it[a];
+    const bool empty = domain_empty(x.domain);
+    AdjArgs<T> A = adj_args<T>(nullptr, nullptr, lam[a], lsj[a], lsk[a], const_cast<stencil_field*>(&x.u_bar),
+                               x.domain, x.coeff, 0.0, empty ? nullptr : x.mask);
+    A.tiles_i = (A.ni + 4 + tile_i - 1) / tile_i;
+    A.ntiles = A.tiles_i * ((A.nj + 4 + tile_j - 1) / tile_j);
+    hargs[e] = A;
+  }
+  // one level-block length for all fields: short enough for a few work items
+  // per resident workgroup, long enough to amortise each item's first level
+  int kper = 32;
+  auto count = [&](int kp) {
+    int64_t t = 0;
+    for (const auto& A : hargs) t += (int64_t)A.ntiles * ((A.nk + kp - 1) / kp);
+    return t;
+  };
+  while (kper > 4 && count(kper) < 8192) kper /= 2;
+  std::vector<int32_t> hitems(mh), hkper(mh);
+  for (int e = 0; e < mh; ++e) {
+    const int kp = std::min(kper, hargs[e].nk);
+    hkper[e] = kp;
+    hitems[e] = hargs[e].ntiles * ((hargs[e].nk + kp - 1) / kp);
+  }
+  const int64_t htotal = count(kper);
+  if (vtotal > INT32_MAX / 2 || htotal > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
+
+  std::vector<uint8_t> blob((size_t)(vbytes + hbytes), 0);
+  write_table(blob, 0, vargs, vitems, {});
+  write_table(blob, (size_t)vbytes, hargs, hitems, hkper);
+  TRY(hip_status(launch_upload(ws, blob.data(), blob.size(), s), "batched table upload"));
+  if (vtotal > 0) {
+    BatchHeader* h = reinterpret_cast<BatchHeader*>(base);
+    const auto* ent = reinterpret_cast<const StepArgs<T>*>(base + table_head_bytes(mv));
+    TRY(hip_status(launch_vadj_batched<T>(h, ent, (int)vtotal, s), "vadv adjoint (batched)"));
+  }
+  BatchHeader* h = reinterpret_cast<BatchHeader*>(base + vbytes);
+  const auto* ent = reinterpret_cast<const AdjArgs<T>*>(base + vbytes + table_head_bytes(mh));
+  return hip_status(launch_hadj_batched<T>(h, ent, (int)htotal, tile_i, s), "hdiff adjoint (batched)");
+}
+
+}  // namespace
+}  // namespace gt4mi
 
 using namespace gt4mi;
 
 extern "C" {
 
-size_t stencil_batch_workspace_bytes(stencil_dtype, int, const stencil_batch_item*) { return 0; }
-size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype, int, const stencil_batch_adjoint_item*) {
-  return 0;
+size_t stencil_batch_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_item* items) {
+  if (check_dtype(dtype) || n <= 0 || n > kMaxBatch || !items) return 0;
+  int m = 0;
+  for (int a = 0; a < n; ++a)
+    if (!domain_empty(items[a].domain)) ++m;
+  return m ? (size_t)table_bytes(m, arg_bytes(dtype, false)) : 0;
 }
-int stencil_step_batched(stencil_dtype, int, const stencil_batch_item*, void*, size_t,
-                         const stencil_options*, hipStream_t) {
-  return fail(STENCIL_E_UNSUPPORTED, "batched launch not built");
+
+size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_adjoint_item* items) {
+  if (check_dtype(dtype) || n <= 0 || n > kMaxBatch || !items) return 0;
+  return adjoint_ws(dtype, n, items);
 }
-int stencil_step_adjoint_batched(stencil_dtype, int, const stencil_batch_adjoint_item*, void*, size_t,
-                                 const stencil_options*, hipStream_t) {
-  return fail(STENCIL_E_UNSUPPORTED, "batched launch not built");
+
+int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws, size_t ws_bytes,
+                         const stencil_options* opts, hipStream_t stream) {
+  TRY(check_batch_args(dtype, n, items, opts));
+  std::vector<ItemSpans> sp;
+  TRY(check_forward_items(dtype, n, items, sp));
+  TRY(check_workspace(ws, ws_bytes, stencil_batch_workspace_bytes(dtype, n, items), sp));
+  if (stencil_batch_workspace_bytes(dtype, n, items) == 0) return ok();
+  TRY(check_device());
+  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP, n, items);
+  return dtype == STENCIL_F64 ? run_step_batched<double>(n, items, ws, ti, stream)
+                              : run_step_batched<float>(n, items, ws, ti, stream);
+}
+
+int stencil_step_adjoint_batched(stencil_dtype dtype, int n, const stencil_batch_adjoint_item* items, void* ws,
+                                 size_t ws_bytes, const stencil_options* opts, hipStream_t stream) {
+  TRY(check_batch_args(dtype, n, items, opts));
+  std::vector<ItemSpans> sp;
+  TRY(check_adjoint_items(dtype, n, items, sp));
+  const size_t need = n ? adjoint_ws(dtype, n, items) : 0;
+  TRY(check_workspace(ws, ws_bytes, need, sp));
+  if (need == 0) return ok();
+  TRY(check_device());
+  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP_ADJOINT, n, items);
+  return dtype == STENCIL_F64 ? run_step_adjoint_batched<double>(n, items, ws, ti, stream)
+                              : run_step_adjoint_batched<float>(n, items, ws, ti, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,203 @@
+// k_batched.hip -- persistent kernels that run a batch of fields of uneven
+// sizes in one launch each.
+//
+// The host sorts the fields longest column first and writes a table into
+// the caller's workspace (a header with the per-field prefix sums of work
+// items, then one argument block per field) with small copy kernels, so the
+// whole call is stream-ordered device work that a HIP graph can capture.
+// Every workgroup of the persistent launch then pulls work items (field,
+// tile[, level block]) from an atomic queue in the header until the queue is
+// exhausted.  A work item runs the same tile body as the single-field
+// kernel, picked by the field's column length.
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "common.hpp"
+#include "k_colsplit.hpp"
+#include "k_hadj.hpp"
+#include "k_split.hpp"
+#include "launch.hpp"
+
+namespace gt4mi {
+
+// ------------------------------------------------------------------ table upload
+#ifdef GT4MI_UPLOAD
+struct ByteChunk {
+  uint32_t nwords;
+  uint32_t words[960];
+};
+
+__global__ void __launch_bounds__(kWG) k_write_words(uint32_t* dst, ByteChunk c) {
+  for (uint32_t t = threadIdx.x; t < c.nwords; t += kWG) dst[t] = c.words[t];
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const uint32_t* w = static_cast<const uint32_t*>(src);
+  const size_t nwords = (bytes + 3) / 4;
+  for (size_t off = 0; off < nwords; off += 960) {
+    ByteChunk c;
+    c.nwords = (uint32_t)((nwords - off) < 960 ? (nwords - off) : 960);
+    memcpy(c.words, w + off, c.nwords * 4);
+    hipLaunchKernelGGL(k_write_words, dim3(1), dim3(kWG), 0, s, static_cast<uint32_t*>(dst) + off, c);
+  }
+  return hipGetLastError();
+}
+#endif
+
+// ------------------------------------------------------------------ queue
+// Next work item of the workgroup (uniform), or -1 when the queue is empty.
+// The table upload of each call zeroes the counter, so no reset is needed.
+__device__ __forceinline__ int next_work(BatchHeader* h, int* slot) {
+  if (threadIdx.x == 0) *slot = (int)atomicAdd(&h->queue, 1u);
+  __syncthreads();
+  const int w = *slot;
+  __syncthreads();  // every lane has the value before the slot is reused
+  return w < h->total ? w : -1;
+}
+
+// Field of work item w: the last e with prefix[e] <= w.
+__device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
+  const int32_t* p = h->prefix();
+  int lo = 0, hi = h->n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ kernels
+// Forward step.  FP64 columns up to 80 levels keep both halves' factors in
+// VGPRs, longer ones (up to 144) stage f in `out`; FP32 keeps all up to 144.
+template <typename T, int TI, int TJ, bool MASK>
+__global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
+  __shared__ SplitSmem<T, TI, TJ> sm;
+  __shared__ int slot;
+  for (;;) {
+    const int w = next_work(h, &slot);
+    if (w < 0) break;
+    const int e = find_entry(h, w);
+    const StepArgs<T> A = ent[e];
+    const int tile = w - h->prefix()[e];
+    if constexpr (sizeof(T) == 8) {
+      if (A.nk <= 80)
+        step_split_tile<T, TI, TJ, 40, GT4MI_PD, MASK, 1>(A, tile, sm);
+      else
+        step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 2>(A, tile, sm);
+    } else {
+      step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 1>(A, tile, sm);
+    }
+    __syncthreads();  // the LDS is reused by the next item
+  }
+}
+
+// Column adjoint lambda = T^{-T} x_bar (argument blocks in column form).
+template <typename T>
+__global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const StepArgs<T>* ent) {
+  __shared__ T xch[2][2][kWG];
+  __shared__ int slot;
+  for (;;) {
+    const int w = next_work(h, &slot);
+    if (w < 0) break;
+    const int e = find_entry(h, w);
+    const StepArgs<T> A = ent[e];
+    const int tile = w - h->prefix()[e];
+    if constexpr (sizeof(T) == 8) {
+      if (A.nk <= 96)
+        column_split_tile<T, 48, GT4MI_PD, true, 1>(A, tile, xch);
+      else
+        column_split_tile<T, 72, GT4MI_PD, true, 2>(A, tile, xch);
+    } else {
+      column_split_tile<T, 72, GT4MI_PD, true, 1>(A, tile, xch);
+    }
+    __syncthreads();
+  }
+}
+
+// Horizontal adjoint: work items (field, tile, level block).
+template <typename T, int TI, int TJ>
+__global__ void __launch_bounds__(TI* TJ) k_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent) {
+  __shared__ HadjSmem<T, TI, TJ> sm;
+  __shared__ int slot;
+  for (;;) {
+    const int w = next_work(h, &slot);
+    if (w < 0) break;
+    const int e = find_entry(h, w);
+    const AdjArgs<T> A = ent[e];
+    const int local = w - h->prefix()[e];
+    const int tile = local % A.ntiles, kb = local / A.ntiles;
+    const int kper = h->kper()[e];
+    hdiff_adjoint_tile<T, TI, TJ>(A, tile, kb * kper, min(kb * kper + kper, A.nk), sm);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+// Resident workgroups per CU times the CU count: the persistent grid.  The
+// occupancy query runs once per device and kernel (and so never inside a
+// stream capture after an eager call).
+template <typename K>
+static int persistent_grid(K kernel, int block, int total) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  int g = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+      int cus = 0, per = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 1;
+      it = cache.emplace(key, cus * per).first;
+    }
+    g = it->second;
+  }
+  return total < g ? (total > 0 ? total : 1) : g;
+}
+
+template <typename T>
+hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                               hipStream_t s) {
+  auto go = [&](auto kernel) {
+    const int grid = persistent_grid(kernel, 2 * kWG, total);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(2 * kWG), 0, s, h, ent);
+    return hipGetLastError();
+  };
+  if (tile_i == 64) return mask ? go(k_step_batched<T, 64, 4, true>) : go(k_step_batched<T, 64, 4, false>);
+  if (tile_i == 32) return mask ? go(k_step_batched<T, 32, 8, true>) : go(k_step_batched<T, 32, 8, false>);
+  return mask ? go(k_step_batched<T, 16, 16, true>) : go(k_step_batched<T, 16, 16, false>);
+}
+
+template <typename T>
+hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s) {
+  const int grid = persistent_grid(k_vadj_batched<T>, 2 * kWG, total);
+  hipLaunchKernelGGL(k_vadj_batched<T>, dim3(grid), dim3(2 * kWG), 0, s, h, ent);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, int tile_i, hipStream_t s) {
+  auto go = [&](auto kernel) {
+    const int grid = persistent_grid(kernel, kWG, total);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, h, ent);
+    return hipGetLastError();
+  };
+  if (tile_i == 64) return go(k_hadj_batched<T, 64, 4>);
+  if (tile_i == 32) return go(k_hadj_batched<T, 32, 8>);
+  return go(k_hadj_batched<T, 16, 16>);
+}
+
+// one object per element type (-DGT4MI_T=float|double); the float one also
+// holds the table upload (-DGT4MI_UPLOAD)
+template hipError_t launch_step_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool, hipStream_t);
+template hipError_t launch_vadj_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, hipStream_t);
+template hipError_t launch_hadj_batched<GT4MI_T>(BatchHeader*, const AdjArgs<GT4MI_T>*, int, int, hipStream_t);
+
+}  // namespace gt4mi

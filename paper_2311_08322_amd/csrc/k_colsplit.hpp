@@ -15,19 +15,19 @@
 
 namespace gt4mi {
 
-template <typename T, int NKH, int PD, bool ADJ>
-__global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
+// COL = 1: e and f of every level in VGPRs; COL = 2: f staged in `out`.
+template <typename T, int NKH, int PD, bool ADJ, int COL>
+__device__ __forceinline__ void column_split_tile(const StepArgs<T>& A, int tile, T (&xch)[2][2][kWG]) {
   constexpr int NT = kWG;
-  __shared__ T xch[2][2][NT];
   const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // 0: top, 1: bottom
   const int ltid = threadIdx.x - half * NT;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int bi = tile % A.tiles_i, bj = tile / A.tiles_i;
   const int i = bi * 64 + (ltid & 63), j = bj * 4 + (ltid >> 6);
   const bool active = (i < A.ni) && (j < A.nj);
   const int ic = min(i, A.ni - 1), jc = min(j, A.nj - 1);
   const int nk = A.nk, m = nk / 2;
   const int nlev = half ? nk - m : m;
+  const int nsteps = nk - m;
   const int k0 = half ? nk - 1 : 0, dir = half ? -1 : 1;
   constexpr uint32_t S = sizeof(T);
   // forward: u (rhs part 1), data (part 2); adjoint: u holds x_bar, data unused
@@ -57,11 +57,13 @@ __global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
 #pragma unroll
   for (int s = 0; s < PD; ++s) issue(s, s);
 
-  T ev[NKH], fv[NKH];
+  T ev[NKH];
+  T fv[COL == 1 ? NKH : 1];
   T wp = T(0), e = T(0), f = T(0);
   const T sn = (half ? A.r4 : -A.r4) * (ADJ ? T(-1) : T(1));
 #pragma unroll
   for (int s = 0; s < NKH; ++s) {
+    if (s >= nsteps) break;  // uniform; the only branch, so load counters stay exact
     __builtin_amdgcn_sched_barrier(0);
     const int slot = s % PD;
     const T rhs = pr[slot], wn = pw[slot];
@@ -78,7 +80,8 @@ __global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
     f = act ? fn : f;
     wp = act ? wn : wp;
     ev[s] = e;
-    fv[s] = f;
+    if constexpr (COL == 1) fv[s] = f;
+    else buf_st(vo.at(min(max(k, 0), nk - 1)), act ? ooff : kOffNone, f);
   }
   xch[half][0][ltid] = e;
   xch[half][1][ltid] = f;
@@ -92,15 +95,28 @@ __global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
 #pragma unroll
   for (int s = NKH - 1; s >= 0; --s) {
     if (s < nlev) {
-      x = fv[s] - ev[s] * x;
-      buf_st(vo.at(k0 + dir * s), ooff, x);
+      const auto ro = vo.at(k0 + dir * s);
+      if constexpr (COL == 1) x = fv[s] - ev[s] * x;
+      else x = buf_ld(ro, ooff, T()) - ev[s] * x;
+      buf_st(ro, ooff, x);
     }
   }
 }
 
+template <typename T, int NKH, int PD, bool ADJ, int COL>
+__global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
+  __shared__ T xch[2][2][kWG];
+  column_split_tile<T, NKH, PD, ADJ, COL>(A, xcd_tile(blockIdx.x, gridDim.x), xch);
+}
+
+// FP64 keeps e and f of both halves in VGPRs up to 96 levels, then stages f
+// in the output up to 144; FP32 keeps both up to 160.
+constexpr int kColsplitRegNkF64 = 96;
+constexpr int kColsplitStagedNkhF64 = 72;
+
 template <typename T>
 constexpr int column_split_max_nk() {
-  return sizeof(T) == 8 ? 96 : 160;  // both halves' factors in <= 256 VGPRs
+  return sizeof(T) == 8 ? 2 * kColsplitStagedNkhF64 : 160;
 }
 
 template <typename T, bool ADJ>
@@ -109,16 +125,21 @@ hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s) {
   A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
   const dim3 grid(A.ntiles), block(2 * kWG);
   const int nkh = A.nk - A.nk / 2;
-#define GT4MI_COLSPLIT_CASE(N)                                                              \
-  if constexpr (2 * N <= column_split_max_nk<T>()) {                                       \
-    if (nkh <= N) {                                                                         \
-      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_PD, ADJ>), grid, block, 0, s, A);     \
-      return hipGetLastError();                                                             \
-    }                                                                                       \
+#define GT4MI_COLSPLIT_CASE(N)                                                                 \
+  if constexpr (2 * N <= (sizeof(T) == 8 ? kColsplitRegNkF64 : 160)) {                         \
+    if (nkh <= N) {                                                                            \
+      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_PD, ADJ, 1>), grid, block, 0, s, A);     \
+      return hipGetLastError();                                                                \
+    }                                                                                          \
   }
-  GT4MI_COLSPLIT_CASE(8) GT4MI_COLSPLIT_CASE(16) GT4MI_COLSPLIT_CASE(24) GT4MI_COLSPLIT_CASE(32)
-  GT4MI_COLSPLIT_CASE(40) GT4MI_COLSPLIT_CASE(48) GT4MI_COLSPLIT_CASE(64) GT4MI_COLSPLIT_CASE(80)
+  GT4MI_COLSPLIT_CASE(16) GT4MI_COLSPLIT_CASE(24) GT4MI_COLSPLIT_CASE(48) GT4MI_COLSPLIT_CASE(80)
 #undef GT4MI_COLSPLIT_CASE
+  if constexpr (sizeof(T) == 8) {
+    if (nkh <= kColsplitStagedNkhF64) {
+      hipLaunchKernelGGL((k_column_split<T, kColsplitStagedNkhF64, GT4MI_PD, ADJ, 2>), grid, block, 0, s, A);
+      return hipGetLastError();
+    }
+  }
   return hipErrorInvalidValue;
 }
 

@@ -46,9 +46,12 @@ struct MaskRec {
     y_off = A.ml.y_off;
     ex_off = A.ml.ex_off;
     ey_off = A.ml.ey_off;
-    win_xy = (uint32_t)plane_xy;
-    win_ex = (uint32_t)A.nj;
-    win_ey = (uint32_t)A.ni;
+    // a field without a mask (batched launches mix them) gets empty windows:
+    // every store falls outside and is dropped
+    const bool has = A.mask != nullptr;
+    win_xy = has ? (uint32_t)plane_xy : 0u;
+    win_ex = has ? (uint32_t)A.nj : 0u;
+    win_ey = has ? (uint32_t)A.ni : 0u;
     shift = (lane / TI) * TI;
     off_row = ((lane % TI) == 0 && j < A.nj) ? (uint32_t)(j * A.ml.words * 8 + (i0 >> 3)) : kOffNone;
     off_ex = (active && i == 0) ? (uint32_t)j : kOffNone;
@@ -76,24 +79,33 @@ struct MaskRec {
   }
 };
 
-// The loop runs every step of the register class with no per-step branch
-// besides the barrier: a step past the half's last level reloads a clamped
-// level and leaves the factors unchanged (selects), so the prefetch stays
-// a fixed distance ahead and the load counters are exact.
-template <typename T, int TI, int TJ, int NKH, int PD, bool MASK>
-__global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
+// The loop runs the steps of the column with no per-step branch besides the
+// barrier and the exit after the last step: a step past the half's last
+// level (odd nk) reloads a clamped level and leaves the factors unchanged
+// (selects), so the prefetch stays a fixed distance ahead and the load
+// counters are exact.
+//
+// COL = 1: both halves keep e and f of every level in VGPRs.
+// COL = 2: e in VGPRs, f staged in `out` (longer columns in the same VGPRs).
+template <typename T, int TI, int TJ>
+struct SplitSmem {
+  T su[2][2][TileAddr<T, TI, TJ>::NLD * kWG];  // [half][step parity]
+  T xch[2][2][kWG];                            // innermost (e, f) of each half and column
+};
+
+template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL>
+__device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, SplitSmem<T, TI, TJ>& sm) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
   static_assert(NT == kWG, "tile must hold 256 columns");
-  __shared__ T su[2][2][NLD * NT];  // [half][step parity]
-  __shared__ T xch[2][2][NT];       // innermost (e, f) of each half and column
 
   const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // 0: top, 1: bottom
   const int ltid = threadIdx.x - half * NT;
   TA t;
-  t.init_lane(ltid, xcd_tile(blockIdx.x, gridDim.x), A.tiles_i, A.ni, A.nj, A.u_sj);
+  t.init_lane(ltid, tile, A.tiles_i, A.ni, A.nj, A.u_sj);
   const int nk = A.nk, m = nk / 2;
   const int nlev = half ? nk - m : m;  // levels this half eliminates
+  const int nsteps = nk - m;           // steps of the workgroup (the larger half)
   const int k0 = half ? nk - 1 : 0, dir = half ? -1 : 1;
   constexpr uint32_t S = sizeof(T);
   const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, -2, -2, A.nj + 4);
@@ -127,7 +139,8 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
 #pragma unroll
   for (int s = 0; s < PD; ++s) issue(s, s);
 
-  T ev[NKH], fv[NKH];
+  T ev[NKH];
+  T fv[COL == 1 ? NKH : 1];
   T wp = T(0), e = T(0), f = T(0);
   const T coeff = A.coeff;
   const T sn = half ? A.r4 : -A.r4;  // near coefficient per unit w: top a = -r/4 w, bottom c = +r/4 w
@@ -136,52 +149,64 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
 
   // Software pipeline: after the barrier of step s the diamond reads of s
   // are issued first and the column elimination of step s-1 runs while
-  // they are in flight; then the diffusion of step s completes.
+  // they are in flight; then the diffusion of step s completes.  The only
+  // branch in the unrolled steps is the exit after the column's last step
+  // (so every step's load counters stay exact); the elimination of that
+  // last step follows the loop.
+  auto eliminate = [&](int sp) {
+    const bool act = sp < nlev;
+    const int k = k0 + dir * sp;
+    const T nr = (sp > 0) ? sn * wp : T(0);                 // a_k (top, k >= 1) / c_k (bottom, k <= nk-2)
+    const T fr = (half == 0 || k > 0) ? -sn * wq : T(0);   // c_k (top) / a_k (bottom, k >= 1)
+    const T b = T(1) + absv(nr) + absv(fr);
+    const T inv = recip(b - nr * e);
+    const T en = fr * inv;
+    const T fn = ((hq + dq) - nr * f) * inv;
+    e = act ? en : e;
+    f = act ? fn : f;
+    wp = act ? wq : wp;
+    return act;
+  };
 #pragma unroll
-  for (int s = 0; s <= NKH; ++s) {
+  for (int s = 0; s < NKH; ++s) {
+    if (s >= nsteps) break;  // uniform
     __builtin_amdgcn_sched_barrier(0);
-    Diamond<T> dm;
-    T dk = T(0), wn = T(0);
-    if (s < NKH) {
-      const int slot = s % PD;
-      T* U = su[half][s & 1];
+    const int slot = s % PD;
+    T* U = sm.su[half][s & 1];
 #pragma unroll
-      for (int q = 0; q < NLD; ++q) U[ltid + q * NT] = pu[slot][q];
-      dk = pd[slot];
-      wn = pw[slot];
-      if (s + PD < NKH) issue(slot, s + PD);
-      __syncthreads();
-      dm = load_diamond<T, HI>(U + cu);
-    }
+    for (int q = 0; q < NLD; ++q) U[ltid + q * NT] = pu[slot][q];
+    const T dk = pd[slot], wn = pw[slot];
+    if (s + PD < NKH) issue(slot, s + PD);
+    __syncthreads();
+    const Diamond<T> dm = load_diamond<T, HI>(U + cu);
     if (s > 0) {
-      const int sp = s - 1;
-      const bool act = sp < nlev;
-      const int k = k0 + dir * sp;
-      const T nr = (sp > 0) ? sn * wp : T(0);                 // a_k (top, k >= 1) / c_k (bottom, k <= nk-2)
-      const T fr = (half == 0 || k > 0) ? -sn * wq : T(0);   // c_k (top) / a_k (bottom, k >= 1)
-      const T b = T(1) + absv(nr) + absv(fr);
-      const T inv = recip(b - nr * e);
-      const T en = fr * inv;
-      const T fn = ((hq + dq) - nr * f) * inv;
-      e = act ? en : e;
-      f = act ? fn : f;
-      wp = act ? wq : wp;
-      ev[sp] = e;
-      fv[sp] = f;
+      const bool act = eliminate(s - 1);
+      ev[s - 1] = e;
+      if constexpr (COL == 1) fv[s - 1] = f;
+      else buf_st(vo.at(min(max(k0 + dir * (s - 1), 0), nk - 1)), act ? ooff : kOffNone, f);
     }
-    if (s < NKH) {
-      bool kxr, kxl, kyr, kyl;
-      hq = hdiff_of(dm, coeff, kxr, kxl, kyr, kyl);
-      dq = dk;
-      wq = wn;
-      if constexpr (MASK) mr.record<TI>(min(max(k0 + dir * s, 0), nk - 1), s < nlev, active, kxr, kyr, kxl, kyl);
-    }
+    bool kxr, kxl, kyr, kyl;
+    hq = hdiff_of(dm, coeff, kxr, kxl, kyr, kyl);
+    dq = dk;
+    wq = wn;
+    if constexpr (MASK) mr.record<TI>(min(max(k0 + dir * s, 0), nk - 1), s < nlev, active, kxr, kyr, kxl, kyl);
+  }
+  {  // the elimination of the last step
+    const int sl = nsteps - 1;
+    const bool act = eliminate(sl);
+#pragma unroll
+    for (int s = 0; s < NKH; ++s)
+      if (s == sl) {
+        ev[s] = e;
+        if constexpr (COL == 1) fv[s] = f;
+      }
+    if constexpr (COL == 2) buf_st(vo.at(min(max(k0 + dir * sl, 0), nk - 1)), act ? ooff : kOffNone, f);
   }
   // interface: the two innermost levels m-1 (top) and m (bottom)
-  xch[half][0][ltid] = e;
-  xch[half][1][ltid] = f;
+  sm.xch[half][0][ltid] = e;
+  sm.xch[half][1][ltid] = f;
   __syncthreads();
-  const T eo = xch[1 - half][0][ltid], fo = xch[1 - half][1][ltid];
+  const T eo = sm.xch[1 - half][0][ltid], fo = sm.xch[1 - half][1][ltid];
   const T et = half ? eo : e, ft = half ? fo : f;  // top's e_{m-1}, f_{m-1} (0 if nk = 1)
   const T eb = half ? e : eo, fb = half ? f : fo;  // bottom's e_m, f_m
   const T xm = (fb - eb * ft) * recip(T(1) - eb * et);
@@ -189,37 +214,57 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   T x = half ? xm1 : xm;  // the value beyond this half's innermost level
 #pragma unroll
   for (int s = NKH - 1; s >= 0; --s) {
-    if (s < nlev) {  // uniform; no loads follow, so the branch costs no waits
-      x = fv[s] - ev[s] * x;
-      buf_st(vo.at(k0 + dir * s), ooff, x);
+    if (s < nlev) {  // uniform
+      const auto ro = vo.at(k0 + dir * s);
+      if constexpr (COL == 1) x = fv[s] - ev[s] * x;
+      else x = buf_ld(ro, ooff, T()) - ev[s] * x;
+      buf_st(ro, ooff, x);
     }
   }
 }
 
-// one instantiation per half-column register class
-#define GT4MI_NKH_CLASSES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80)
+
+template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL>
+__global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
+  __shared__ SplitSmem<T, TI, TJ> sm;
+  step_split_tile<T, TI, TJ, NKH, PD, MASK, COL>(A, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+// One instantiation per half-column register class.  With the early exit a
+// class costs only its registers, so the classes are coarse.  FP64 keeps e
+// and f of both halves in VGPRs up to 80 levels; longer FP64 columns (up to
+// 144) keep e and stage f in the output.
+#define GT4MI_NKH_CLASSES(X) X(16) X(24) X(40) X(56) X(80)
+constexpr int kSplitRegNkF64 = 80;
+constexpr int kSplitStagedNkhF64 = 72;
 
 template <typename T>
 constexpr int split_max_nk() {
-  return sizeof(T) == 8 ? 80 : 160;  // both halves' factors in <= 256 VGPRs
+  return sizeof(T) == 8 ? 2 * kSplitStagedNkhF64 : 160;
 }
 
 template <typename T, int TI, int TJ>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s) {
   const dim3 grid(A.ntiles), block(2 * TI * TJ);
   const int nkh = A.nk - A.nk / 2;
-#define GT4MI_SPLIT_CASE(N)                                                                       \
-  if constexpr (2 * N <= split_max_nk<T>()) {                                                     \
-    if (nkh <= N) {                                                                               \
-      if (A.mask)                                                                                 \
-        hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, true>), grid, block, 0, s, A);  \
-      else                                                                                        \
-        hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, false>), grid, block, 0, s, A); \
-      return hipGetLastError();                                                                   \
-    }                                                                                             \
+#define GT4MI_SPLIT_LAUNCH(N, C)                                                                     \
+  {                                                                                                  \
+    if (A.mask)                                                                                      \
+      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, true, C>), grid, block, 0, s, A);    \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, false, C>), grid, block, 0, s, A);   \
+    return hipGetLastError();                                                                        \
+  }
+#define GT4MI_SPLIT_CASE(N)                                                                  \
+  if constexpr (2 * N <= (sizeof(T) == 8 ? kSplitRegNkF64 : 160)) {                          \
+    if (nkh <= N) GT4MI_SPLIT_LAUNCH(N, 1)                                                   \
   }
   GT4MI_NKH_CLASSES(GT4MI_SPLIT_CASE)
+  if constexpr (sizeof(T) == 8) {
+    if (nkh <= kSplitStagedNkhF64) GT4MI_SPLIT_LAUNCH(kSplitStagedNkhF64, 2)
+  }
 #undef GT4MI_SPLIT_CASE
+#undef GT4MI_SPLIT_LAUNCH
   return hipErrorInvalidValue;
 }
 

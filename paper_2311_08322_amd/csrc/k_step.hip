@@ -16,7 +16,7 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
   const int tj = kWG / tile_i;
   A.tiles_i = (A.ni + tile_i - 1) / tile_i;
   A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
-  if (col == 3 && A.nk <= (sizeof(T) == 8 ? 80 : 160)) {  // STENCIL_COLUMN_SPLIT
+  if (col == 3 && A.nk <= split_step_limit(sizeof(T))) {  // STENCIL_COLUMN_SPLIT
     if (tile_i == 64) return launch_split_classes<T, 64, 4>(A, s);
     if (tile_i == 32) return launch_split_classes<T, 32, 8>(A, s);
     return launch_split_classes<T, 16, 16>(A, s);

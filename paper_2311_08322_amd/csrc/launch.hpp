@@ -21,10 +21,12 @@ hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int TI, int TJ>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
 // two-ended column solve: ADJ = false, out = T^{-1}(u + data);
-// ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 96 (FP64) / 160 (FP32)
+// ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 144 (FP64) / 160 (FP32)
 template <typename T, bool ADJ>
 hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s);
-constexpr int column_split_limit(int elem_bytes) { return elem_bytes == 8 ? 96 : 160; }
+constexpr int column_split_limit(int elem_bytes) { return elem_bytes == 8 ? 144 : 160; }
+// two-ended fused step (k_split.hpp): nk <= 144 (FP64) / 160 (FP32)
+constexpr int split_step_limit(int elem_bytes) { return elem_bytes == 8 ? 144 : 160; }
 template <typename T>
 hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s);
 template <typename T>
@@ -52,6 +54,30 @@ template <typename T, int COL>
 hipError_t launch_vadj_classes(const AdjArgs<T>& A, hipStream_t s);
 template <typename T>
 hipError_t launch_hdiff_adjoint(AdjArgs<T> A, int tile_i, hipStream_t s);
+
+// persistent batched launches (k_batched.hip).  The work list sits in device
+// memory: a BatchHeader, then prefix[n + 1] (first work item of each field)
+// and kper[n] (levels per work item, horizontal adjoint only).
+struct BatchHeader {
+  uint32_t queue;  // next work item, taken with atomicAdd
+  int32_t n;       // fields
+  int32_t total;   // work items
+  int32_t pad;
+  __host__ __device__ const int32_t* prefix() const { return reinterpret_cast<const int32_t*>(this + 1); }
+  __host__ __device__ const int32_t* kper() const { return prefix() + n + 1; }
+};
+// longest column of a batched field (both halves' e in VGPRs, f staged)
+constexpr int kMaxBatchedNk = 144;
+// stream-ordered copy of a small host table into device memory (kernel
+// arguments, so that a captured graph holds its own copy)
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s);
+template <typename T>
+hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, int tile_i, hipStream_t s);
 
 // fill a strided box with a deterministic pattern (autotuner scratch)
 template <typename T>

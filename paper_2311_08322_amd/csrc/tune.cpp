@@ -148,7 +148,7 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   std::vector<Cand> cands;
   for (int t : {64, 32, 16}) {
     if (op == STENCIL_OP_STEP) {
-      if (nk <= (dtype == STENCIL_F64 ? 80 : 160)) cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT});
+      if (nk <= split_step_limit((int)(dtype == STENCIL_F64 ? 8 : 4))) cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT});
       if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS});
       if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF});
     } else {

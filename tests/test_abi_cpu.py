@@ -268,3 +268,78 @@ def test_binding_refuses_unknown_dtype():
     with pytest.raises(api.StencilError):
         api.stencil_hdiff(api.Field(t, (2, 2, 0)), api.Field(t.clone(), (2, 2, 0)), (4, 4, 2), 0.025,
                           stream=0)
+
+
+# ----------------------------------------------------------------- batched
+def batch_items(sizes, base=BASE):
+    arr = (_lib.StencilBatchItem * len(sizes))()
+    for n, (ni, nj, nk) in enumerate(sizes):
+        u, data, w, out, d = fields(ni, nj, nk)
+        off = base + n * (1 << 32)  # each item in its own 4 GiB window
+        for f in (u, data, w, out):
+            f.data = f.data - BASE + off
+        arr[n].u, arr[n].data, arr[n].w, arr[n].out = u, data, w, out
+        arr[n].domain = _lib.I64x3(ni, nj, nk)
+        arr[n].coeff, arr[n].dt_dz = 0.025, 0.5
+    return arr
+
+
+def test_batch_validation(L):
+    items = batch_items([(16, 12, 8), (20, 9, 30)])
+    need = L.stencil_batch_workspace_bytes(1, 2, items)
+    assert need > 0 and need % 256 == 0
+    ws = BASE + (64 << 32)
+    run = lambda arr, n=2, ws=ws, nb=need, o=None: L.stencil_step_batched(  # noqa: E731
+        1, n, arr, ws, nb, ctypes.byref(o) if o else None, None)
+    assert run(items, nb=need - 1) == code("STENCIL_E_WORKSPACE")
+    assert run(items, ws=None) == code("STENCIL_E_WORKSPACE")
+    assert run(items, ws=ws + 8) == code("STENCIL_E_WORKSPACE")  # the table wants 256-B alignment
+    assert run(items, n=-1) == code("STENCIL_E_ARG")
+    assert run(None, n=2) == code("STENCIL_E_NULL")
+    o = _lib.StencilOptions()
+    o.impl = _lib.IMPL_PLAIN
+    assert run(items, o=o) == code("STENCIL_E_UNSUPPORTED")
+    # the workspace may not overlap any field
+    assert run(items, ws=items[1].u.data) == code("STENCIL_E_ALIAS")
+    # one item's output may not touch another item's buffers (all run at once)
+    bad = batch_items([(16, 12, 8), (20, 9, 30)])
+    bad[1].out.data = bad[0].u.data
+    assert run(bad) == code("STENCIL_E_ALIAS")
+    assert "item 1" in _lib.last_error() and "item 0" in _lib.last_error()
+    bad = batch_items([(16, 12, 8), (20, 9, 30)])
+    bad[0].mask = bad[1].w.data
+    assert run(bad) == code("STENCIL_E_ALIAS")
+    # per-item rules name the item
+    bad = batch_items([(16, 12, 8), (20, 9, 30)])
+    bad[1].u.origin = _lib.I64x3(1, 2, 0)
+    assert run(bad) == code("STENCIL_E_HALO")
+    assert _lib.last_error().startswith("item 1")
+    # columns longer than the batched classes
+    long = batch_items([(16, 12, 8), (8, 8, 145)])
+    assert run(long, nb=L.stencil_batch_workspace_bytes(1, 2, long)) == code("STENCIL_E_UNSUPPORTED")
+    # a batch with no interior work is a no-op that needs no workspace (and no device)
+    empty = batch_items([(0, 12, 8), (20, 9, 0)])
+    assert L.stencil_batch_workspace_bytes(1, 2, empty) == 0
+    assert run(empty, ws=None, nb=0) == 0
+    assert L.stencil_step_batched(1, 0, None, None, 0, None, None) == 0
+
+
+def test_batch_adjoint_workspace_and_validation(L):
+    fw = batch_items([(16, 12, 8), (20, 9, 30)])
+    arr = (_lib.StencilBatchAdjointItem * 2)()
+    for n in range(2):
+        arr[n].x_bar, arr[n].w, arr[n].u_bar = fw[n].data, fw[n].w, fw[n].u
+        arr[n].domain, arr[n].coeff, arr[n].dt_dz = fw[n].domain, 0.025, 0.5
+        arr[n].mask = fw[n].out.data  # distinct memory standing in for a mask
+    without = L.stencil_batch_adjoint_workspace_bytes(1, 2, arr)
+    # lambda of both items lives in the workspace when data_bar is absent
+    assert without >= 8 * (16 * 12 * 8 + 20 * 9 * 30)
+    arr[0].data_bar = fld(16, 12, 8, halo=0, base=BASE + (40 << 32))
+    assert without - L.stencil_batch_adjoint_workspace_bytes(1, 2, arr) >= 8 * 16 * 12 * 8
+    ws = BASE + (64 << 32)
+    need = L.stencil_batch_adjoint_workspace_bytes(1, 2, arr)
+    arr[1].mask = None
+    assert L.stencil_step_adjoint_batched(1, 2, arr, ws, need, None, None) == code("STENCIL_E_NULL")
+    arr[1].mask = fw[1].out.data
+    arr[1].u_bar = fld(20, 9, 30, base=fw[0].u.data)  # two items writing one buffer
+    assert L.stencil_step_adjoint_batched(1, 2, arr, ws, need, None, None) == code("STENCIL_E_ALIAS")
