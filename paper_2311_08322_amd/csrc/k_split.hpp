@@ -87,6 +87,16 @@ struct MaskRec {
 //
 // COL = 1: both halves keep e and f of every level in VGPRs.
 // COL = 2: e in VGPRs, f staged in `out` (longer columns in the same VGPRs).
+// Cache policy of the streamed accesses: data, w and out are touched once
+// (GT4MI_CP_ONCE), u's halo rows are shared with the neighbouring tiles
+// through L2 (GT4MI_CP_HALO).
+#ifndef GT4MI_CP_ONCE
+#define GT4MI_CP_ONCE 0
+#endif
+#ifndef GT4MI_CP_HALO
+#define GT4MI_CP_HALO 0
+#endif
+
 template <typename T, int TI, int TJ>
 struct SplitSmem {
   T su[2][2][TileAddr<T, TI, TJ>::NLD * kWG];  // [half][step parity]
@@ -128,9 +138,9 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
   auto issue = [&](int slot, int s) {
     const auto ru = cur_u.rsrc();
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) pu[slot][q] = buf_ld(ru, t.hoff[q], T());
-    pd[slot] = buf_ld(cur_d.rsrc(), doff, T());
-    pw[slot] = buf_ld(cur_w.rsrc(), woff, T());  // the w level new at this step
+    for (int q = 0; q < NLD; ++q) pu[slot][q] = buf_ld<GT4MI_CP_HALO>(ru, t.hoff[q], T());
+    pd[slot] = buf_ld<GT4MI_CP_ONCE>(cur_d.rsrc(), doff, T());
+    pw[slot] = buf_ld<GT4MI_CP_ONCE>(cur_w.rsrc(), woff, T());  // the w level new at this step
     const bool go = s + 1 < nlev;
     cur_u.advance(go);
     cur_d.advance(go);
@@ -218,7 +228,7 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
       const auto ro = vo.at(k0 + dir * s);
       if constexpr (COL == 1) x = fv[s] - ev[s] * x;
       else x = buf_ld(ro, ooff, T()) - ev[s] * x;
-      buf_st(ro, ooff, x);
+      buf_st<GT4MI_CP_ONCE>(ro, ooff, x);
     }
   }
 }

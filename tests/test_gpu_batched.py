@@ -50,14 +50,19 @@ def _oracle_forward(batch, dtype):
     return _ORACLE[key]
 
 
+def _storage(ni, nj, nk):
+    """Storage extents of a field whose domain may be empty: at least one
+    point along each axis (a field's data pointer may not be NULL)."""
+    return max(ni, 1), max(nj, 1), max(nk, 1)
+
+
 def _items(batch, dtype, masks=True):
-    """Device fields of a batch; a field with no levels keeps one level of
-    storage (a field's data pointer may not be NULL)."""
+    """Device fields of a batch (fields drawn at their storage extents)."""
     items = []
     for ni, nj, nk, f in batch:
         u, data, w = dev_fields(f, dtype, DEV)
         dims = (ni, nj, nk)
-        out = fields.alloc(ni, nj, nk, dtype, DEV, fill=0.0, kextra=int(nk == 0))
+        out = fields.alloc(*_storage(ni, nj, nk), dtype, DEV, fill=0.0)
         items.append(dict(u=u, data=data, w=w, out=out, domain=dims,
                           coeff=inputs.COEFF, dt_dz=inputs.DT_DZ,
                           mask=fields.mask_tensor(dims, DEV) if masks else None))
@@ -116,12 +121,11 @@ def _adjoint_items(items, dtype, with_dbar):
     adj = []
     for n, it in enumerate(items):
         ni, nj, nk = it["domain"]
-        kx = int(nk == 0)
-        ob = inputs.cotangent(ni, nj, nk + kx)
+        st = _storage(ni, nj, nk)
+        ob = inputs.cotangent(*st)
         adj.append(dict(x_bar=fields.from_interior(ob, dtype, DEV), w=it["w"], mask=it["mask"],
-                        u_bar=fields.alloc(ni, nj, nk, dtype, DEV, fill=123.0, kextra=kx),
-                        data_bar=fields.alloc(ni, nj, nk, dtype, DEV, halo=0, fill=0.0, kextra=kx)
-                        if with_dbar else None,
+                        u_bar=fields.alloc(*st, dtype, DEV, fill=123.0),
+                        data_bar=fields.alloc(*st, dtype, DEV, halo=0, fill=0.0) if with_dbar else None,
                         domain=it["domain"], coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, ob=ob))
     return adj
 
@@ -179,8 +183,7 @@ SMALL = [(67, 45, 7), (1, 1, 1), (0, 12, 8), (33, 17, 144), (20, 9, 0), (130, 3,
 
 
 def _small_batch(seed):
-    # fields of no levels are drawn with one level of storage
-    return [(ni, nj, nk, inputs.fields_sized(ni, nj, max(nk, 1), seed=seed + n))
+    return [(ni, nj, nk, inputs.fields_sized(*_storage(ni, nj, nk), seed=seed + n))
             for n, (ni, nj, nk) in enumerate(SMALL)]
 
 
