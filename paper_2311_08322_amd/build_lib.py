@@ -39,7 +39,6 @@ def _units():
         for adj in ("false", "true"):
             u.append(("k_step_inst.hip", f"colsplit_{t}_{adj}",
                       [f"-DGT4MI_T={t}", "-DGT4MI_COLSPLIT", f"-DGT4MI_ADJ={adj}", *UNROLL]))
-        u.append(("k_step_inst.hip", f"rows_{t}", [f"-DGT4MI_T={t}", "-DGT4MI_ROWS", *UNROLL]))
         for ti in (64, 32, 16):
             u.append(("k_step_inst.hip", f"split_{t}_{ti}",
                       [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", *UNROLL]))

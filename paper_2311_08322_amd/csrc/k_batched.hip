@@ -11,15 +11,12 @@
 // kernel, picked by the field's column length.
 #include <string.h>
 
-#include <map>
-#include <mutex>
-#include <utility>
-
 #include "common.hpp"
 #include "k_colsplit.hpp"
 #include "k_hadj.hpp"
 #include "k_split.hpp"
 #include "launch.hpp"
+#include "persist.hpp"
 
 namespace gt4mi {
 
@@ -137,31 +134,6 @@ __global__ void __launch_bounds__(TI* TJ) k_hadj_batched(BatchHeader* h, const A
 }
 
 // ------------------------------------------------------------------ launchers
-// Resident workgroups per CU times the CU count: the persistent grid.  The
-// occupancy query runs once per device and kernel (and so never inside a
-// stream capture after an eager call).
-template <typename K>
-static int persistent_grid(K kernel, int block, int total) {
-  static std::mutex mu;
-  static std::map<std::pair<int, const void*>, int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1;
-  int g = 0;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    const auto key = std::make_pair(dev, reinterpret_cast<const void*>(kernel));
-    auto it = cache.find(key);
-    if (it == cache.end()) {
-      int cus = 0, per = 0;
-      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 1;
-      it = cache.emplace(key, cus * per).first;
-    }
-    g = it->second;
-  }
-  return total < g ? (total > 0 ? total : 1) : g;
-}
-
 template <typename T>
 hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
                                hipStream_t s) {

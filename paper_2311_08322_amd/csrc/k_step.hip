@@ -2,10 +2,6 @@
 // register classes themselves are instantiated in k_step_inst.hip).
 #include "launch.hpp"
 
-#ifndef GT4MI_ROWS_DEFAULT
-#define GT4MI_ROWS_DEFAULT 0
-#endif
-
 namespace gt4mi {
 
 template <typename T, int COL>
@@ -21,9 +17,6 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
   A.tiles_i = (A.ni + tile_i - 1) / tile_i;
   A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
   if (col == 3 && A.nk <= split_step_limit(sizeof(T))) {  // STENCIL_COLUMN_SPLIT
-#if GT4MI_ROWS_DEFAULT
-    if (tile_i == 64) return launch_rows_classes<T>(A, s);
-#endif
     if (tile_i == 64) return launch_split_classes<T, 64, 4>(A, s);
     if (tile_i == 32) return launch_split_classes<T, 32, 8>(A, s);
     return launch_split_classes<T, 16, 16>(A, s);

@@ -4,17 +4,13 @@
 //   -DGT4MI_T=... -DGT4MI_VADV -DGT4MI_COL=1|2                   (vadv)
 //   -DGT4MI_T=... -DGT4MI_TI=64|32|16 -DGT4MI_SPLIT               (two-ended step)
 //   -DGT4MI_T=... -DGT4MI_COLSPLIT -DGT4MI_ADJ=false|true          (two-ended column solves)
-//   -DGT4MI_T=... -DGT4MI_ROWS                                      (two-ended step, DPP rows)
 // Splitting keeps each fully unrolled register class in a parallel job.
 #include "k_colsplit.hpp"
-#include "k_rows.hpp"
 #include "k_split.hpp"
 
 namespace gt4mi {
 
-#if defined(GT4MI_ROWS)
-template hipError_t launch_rows_classes<GT4MI_T>(const StepArgs<GT4MI_T>&, hipStream_t);
-#elif defined(GT4MI_COLSPLIT)
+#if defined(GT4MI_COLSPLIT)
 template hipError_t launch_column_split_classes<GT4MI_T, GT4MI_ADJ>(StepArgs<GT4MI_T>, hipStream_t);
 #elif defined(GT4MI_SPLIT)
 template hipError_t launch_split_classes<GT4MI_T, GT4MI_TI, 256 / GT4MI_TI>(const StepArgs<GT4MI_T>&,

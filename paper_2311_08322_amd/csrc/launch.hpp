@@ -20,10 +20,6 @@ template <typename T, int COL>
 hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int TI, int TJ>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
-// the two-ended step with the horizontal neighbours exchanged by DPP within
-// each wave (tile 64 x 4; k_rows.hpp)
-template <typename T>
-hipError_t launch_rows_classes(const StepArgs<T>& A, hipStream_t s);
 // two-ended column solve: ADJ = false, out = T^{-1}(u + data);
 // ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 144 (FP64) / 160 (FP32)
 template <typename T, bool ADJ>
