@@ -396,4 +396,88 @@ void oracle_laplacian(int ni, int nj, int nk, const double* u, double* lap) {
             (size_t)(i + 1)] = lap64(u, ni, nj, i, j, k);
 }
 
+/* ------------------------------------------------------------------ */
+/* Parameter gradients of one step (parameter tuning).                  */
+/* With the limiter decisions held fixed the diffusion is               */
+/*   h = u - coeff * D(u),  D(u)(p) = (Fx(p) - Fx(p-ei)) + (Fy(p) - Fy(p-ej)) */
+/* (the limited fluxes do not depend on coeff), and the column solve is */
+/* T(w) x = h + data.  For a scalar loss L with xbar = dL/dx and        */
+/* lam = T^{-T} xbar:                                                   */
+/*   dL/dcoeff = sum_p lam(p) dh(p)/dcoeff = -sum_p lam(p) D(u)(p),      */
+/*   dL/dT(k,l) = -lam_k x_l for every nonzero entry of T: a_k (l=k-1), */
+/*   b_k (l=k), c_k (l=k+1), chained through the coefficient            */
+/*   definitions a_k = -r/4 w_k, c_k = r/4 w_{k+1}, b_k = 1+|a_k|+|c_k| */
+/*   (d|t|/dt = sign t, taken as 0 at t = 0).                           */
+/* ------------------------------------------------------------------ */
+
+/* D(u) on the interior with the given masks (interior layout). */
+void oracle_hdiff_divergence(int ni, int nj, int nk, const double* u, const unsigned char* mx,
+                             const unsigned char* my, double* div) {
+  if ((size_t)ni * (size_t)nj * (size_t)nk == 0) return;
+  /* h = u - 1 * D would round; take the flux differences directly */
+  const int li = ni + 2, lj = nj + 2;
+  double* lap = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
+#define LAPD(i, j) lap[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)]
+  for (int k = 0; k < nk; ++k) {
+    for (int j = -1; j <= nj; ++j)
+      for (int i = -1; i <= ni; ++i) LAPD(i, j) = lap64(u, ni, nj, i, j, k);
+    for (int j = 0; j < nj; ++j)
+      for (int i = 0; i < ni; ++i) {
+        double fxr = mx[MXIDX(i, j, k)] ? LAPD(i + 1, j) - LAPD(i, j) : 0.0;
+        double fxl = mx[MXIDX(i - 1, j, k)] ? LAPD(i, j) - LAPD(i - 1, j) : 0.0;
+        double fyr = my[MYIDX(i, j, k)] ? LAPD(i, j + 1) - LAPD(i, j) : 0.0;
+        double fyl = my[MYIDX(i, j - 1, k)] ? LAPD(i, j) - LAPD(i, j - 1) : 0.0;
+        div[IIDX(i, j, k)] = (fxr - fxl) + (fyr - fyl);
+      }
+  }
+#undef LAPD
+  free(lap);
+}
+
+/* dL/dcoeff = -sum lam * D(u), D with the masks given; the sum is
+ * compensated (Neumaier) so that it is accurate to about one rounding. */
+double oracle_coeff_grad(int ni, int nj, int nk, const double* u, const double* lam,
+                         const unsigned char* mx, const unsigned char* my) {
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  if (n == 0) return 0.0;
+  double* div = (double*)malloc(sizeof(double) * n);
+  oracle_hdiff_divergence(ni, nj, nk, u, mx, my, div);
+  double s = 0.0, comp = 0.0;
+  for (size_t p = 0; p < n; ++p) {
+    double t = -(lam[p] * div[p]);
+    double v = s + t;
+    comp += fabs(s) >= fabs(t) ? (s - v) + t : (t - v) + s;
+    s = v;
+  }
+  free(div);
+  return s + comp;
+}
+
+static double sgn(double t) { return t > 0.0 ? 1.0 : (t < 0.0 ? -1.0 : 0.0); }
+
+/* dL/dw on the staggered levels 0..nk (w_0 and w_nk do not enter T, so
+ * their gradient is 0); lam and x interior, wbar staggered. */
+void oracle_w_grad(int ni, int nj, int nk, const double* w, const double* x, const double* lam,
+                   double dt_dz, double* wbar) {
+  const size_t plane = (size_t)ni * (size_t)nj;
+  for (size_t p = 0; p < plane * (size_t)(nk + 1); ++p) wbar[p] = 0.0;
+  const double q = 0.25 * dt_dz;
+  for (int j = 0; j < nj; ++j)
+    for (int i = 0; i < ni; ++i)
+      for (int k = 0; k < nk; ++k) {
+        const double lk = lam[IIDX(i, j, k)];
+        const double a = coef_a(w, ni, nj, i, j, k, dt_dz);
+        const double c = coef_c(w, ni, nj, nk, i, j, k, dt_dz);
+        const double bbar = -lk * x[IIDX(i, j, k)];
+        if (k >= 1) { /* a_k = -q w_k, |a_k| in b_k */
+          const double abar = -lk * x[IIDX(i, j, k - 1)];
+          wbar[(size_t)k * plane + (size_t)j * (size_t)ni + (size_t)i] += -q * abar + sgn(a) * (-q) * bbar;
+        }
+        if (k <= nk - 2) { /* c_k = q w_{k+1}, |c_k| in b_k */
+          const double cbar = -lk * x[IIDX(i, j, k + 1)];
+          wbar[(size_t)(k + 1) * plane + (size_t)j * (size_t)ni + (size_t)i] += q * cbar + sgn(c) * q * bbar;
+        }
+      }
+}
+
 int oracle_version(void) { return 1; }

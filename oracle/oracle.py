@@ -64,11 +64,15 @@ def lib():
             "oracle_hdiff_tangent": [I, I, I, dp, bp, bp, D, dp],
             "oracle_tridiag_apply": [I, I, I, dp, dp, D, dp],
             "oracle_laplacian": [I, I, I, dp, dp],
+            "oracle_hdiff_divergence": [I, I, I, dp, bp, bp, dp],
+            "oracle_w_grad": [I, I, I, dp, dp, dp, D, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = None
+        L.oracle_coeff_grad.argtypes = [I, I, I, dp, dp, bp, bp]
+        L.oracle_coeff_grad.restype = D
         _lib = L
     return _lib
 
@@ -216,3 +220,35 @@ def laplacian(u):
     lap = np.zeros((nk, nj + 2, ni + 2))
     lib().oracle_laplacian(ni, nj, nk, _d(u), _d(lap))
     return lap
+
+
+def hdiff_divergence(u, mx, my):
+    """D(u): the divergence of the limited fluxes on the interior."""
+    ni, nj, nk = _dims_padded(u)
+    u = _f64(u, (nk, nj + 4, ni + 4))
+    mx = _u8(mx, (nk, nj, ni + 1))
+    my = _u8(my, (nk, nj + 1, ni))
+    div = np.zeros((nk, nj, ni))
+    lib().oracle_hdiff_divergence(ni, nj, nk, _d(u), _b(mx), _b(my), _d(div))
+    return div
+
+
+def coeff_grad(u, lam, mx, my):
+    """dL/dcoeff = -sum lam * D(u) (compensated sum)."""
+    ni, nj, nk = _dims_padded(u)
+    u = _f64(u, (nk, nj + 4, ni + 4))
+    lam = _f64(lam, (nk, nj, ni))
+    mx = _u8(mx, (nk, nj, ni + 1))
+    my = _u8(my, (nk, nj + 1, ni))
+    return float(lib().oracle_coeff_grad(ni, nj, nk, _d(u), _d(lam), _b(mx), _b(my)))
+
+
+def w_grad(w, x, lam, dt_dz):
+    """dL/dw on the nk+1 staggered levels (x: the step output, interior)."""
+    nk, nj, ni = np.shape(x)
+    w = _f64(w, (nk + 1, nj, ni))
+    x = _f64(x, (nk, nj, ni))
+    lam = _f64(lam, (nk, nj, ni))
+    wbar = np.zeros((nk + 1, nj, ni))
+    lib().oracle_w_grad(ni, nj, nk, _d(w), _d(x), _d(lam), float(dt_dz), _d(wbar))
+    return wbar

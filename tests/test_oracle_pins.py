@@ -366,3 +366,84 @@ def test_corner_halo_points_never_read(oracle):
         u2[:, jj, ii] = 1e6
     nxt, _, _ = oracle.step(u2, f.data, f.w, COEFF, DT_DZ)
     assert np.array_equal(_interior(nxt), _interior(base))
+
+
+# ---------------------------------------------------------------- parameter gradients
+def _loss(oracle, f, ob, coeff, w):
+    nxt, _, _ = oracle.step(f.u, f.data, w, coeff, DT_DZ)
+    return math.fsum((_interior(nxt) * ob).ravel())
+
+
+def test_divergence_closed_forms(oracle):
+    """D(u) = (u - hdiff(u)) / coeff: 0 for a linear field, -24 for the
+    quartic (i+4)^4 whose fluxes are all kept (P5)."""
+    ni, nj, nk = 9, 8, 2
+    I, J = _grid(ni, nj, nk)
+    lin = 3.0 * I - 7.0 * J + 2.0  # integers: every stage is exact
+    mx, my = oracle.hdiff_masks(lin)
+    assert np.all(oracle.hdiff_divergence(lin, mx, my) == 0.0)
+    q = (I + 4.0) ** 4
+    mx, my = oracle.hdiff_masks(q)
+    np.testing.assert_allclose(oracle.hdiff_divergence(q, mx, my), -24.0, rtol=0, atol=1e-9)
+
+
+def test_coeff_gradient_is_exact_difference_quotient(oracle):
+    """The limiter decisions do not depend on coeff, so <ob, step> is affine
+    in coeff: its central difference quotient is exact up to rounding, and
+    L(c) = L(0) + c dL/dcoeff."""
+    ni, nj, nk = 14, 11, 9
+    f = inputs.fields_sized(ni, nj, nk, seed=80)
+    ob = inputs.cotangent(ni, nj, nk)
+    mx, my = oracle.hdiff_masks(f.u)
+    lam = oracle.vadv_adjoint(ob, f.w, DT_DZ)
+    g = oracle.coeff_grad(f.u, lam, mx, my)
+    h = 0.01
+    fd = (_loss(oracle, f, ob, COEFF + h, f.w) - _loss(oracle, f, ob, COEFF - h, f.w)) / (2 * h)
+    assert abs(fd - g) <= 1e-9 * max(1.0, abs(g)), (fd, g)
+    l0 = _loss(oracle, f, ob, 0.0, f.w)
+    lc = _loss(oracle, f, ob, COEFF, f.w)
+    assert abs((lc - l0) - COEFF * g) <= 1e-11 * max(1.0, abs(lc))
+
+
+def test_w_gradient_central_differences_every_level(oracle):
+    """Central differences (h = 1e-6) of <ob, step(w)> for every staggered
+    level of every column, including w_0 and w_nk, which do not enter T."""
+    ni, nj, nk = 5, 4, 6
+    f = inputs.fields_sized(ni, nj, nk, seed=81)
+    ob = inputs.cotangent(ni, nj, nk)
+    nxt, _, _ = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    lam = oracle.vadv_adjoint(ob, f.w, DT_DZ)
+    wbar = oracle.w_grad(f.w, _interior(nxt), lam, DT_DZ)
+    assert np.all(wbar[0] == 0.0) and np.all(wbar[nk] == 0.0)
+    h = 1e-6
+    checked = 0
+    for p in range(f.w.size):
+        if abs(f.w.ravel()[p]) < 1e-3:
+            continue  # |a| or |c| has a kink at w = 0
+        wp = f.w.copy().ravel()
+        wm = f.w.copy().ravel()
+        wp[p] += h
+        wm[p] -= h
+        fd = (_loss(oracle, f, ob, COEFF, wp.reshape(f.w.shape)) -
+              _loss(oracle, f, ob, COEFF, wm.reshape(f.w.shape))) / (2 * h)
+        g = wbar.ravel()[p]
+        assert abs(fd - g) <= 1e-7 * max(1.0, abs(g)), (p, fd, g)
+        checked += 1
+    assert checked >= f.w.size - 4
+
+
+def test_w_gradient_at_zero_velocity(oracle):
+    """w = 0: T = I, x = d, lam = ob, and with d|t|/dt = 0 at 0 only the
+    off-diagonal entries contribute: wbar_j = r/4 (lam_j x_{j-1} - lam_{j-1} x_j)."""
+    ni, nj, nk = 3, 2, 5
+    f = inputs.fields_sized(ni, nj, nk, seed=82)
+    w0 = np.zeros_like(f.w)
+    ob = inputs.cotangent(ni, nj, nk)
+    nxt, _, _ = oracle.step(f.u, f.data, w0, COEFF, DT_DZ)
+    x = _interior(nxt)
+    lam = oracle.vadv_adjoint(ob, w0, DT_DZ)
+    assert np.array_equal(lam, ob)
+    wbar = oracle.w_grad(w0, x, lam, DT_DZ)
+    want = np.zeros_like(w0)
+    want[1:nk] = 0.25 * DT_DZ * (lam[1:] * x[:-1] - lam[:-1] * x[1:])
+    np.testing.assert_allclose(wbar, want, rtol=0, atol=1e-15)
