@@ -193,6 +193,32 @@ int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
                          stencil_field* data_bar, const int64_t domain[3], double coeff,
                          double dt_dz, const stencil_options* opts, hipStream_t stream);
 
+/* ------------------------------------------------------ parameter gradients */
+/* Gradients of a scalar loss L with respect to the parameters of one step
+ * (parameter tuning).  With the limiter decisions held fixed the diffusion
+ * is h = u - coeff D(u), D the divergence of the limited fluxes (it does not
+ * depend on coeff), and the column solve is T(w) x = h + data.  With x_bar
+ * = dL/dx, lam = T^{-T} x_bar (the data_bar output of stencil_step_adjoint)
+ * and x the step's output:
+ *   coeff_bar = -sum over the domain of lam * D(u)
+ *   w_bar_j   = r/4 [lam_j x_{j-1} - lam_{j-1} x_j - s_j (lam_j x_j + lam_{j-1} x_{j-1})]
+ * for j = 1 .. nk-1, r = dt_dz, s_j = sign w_j (0 at 0: the a.e. derivative
+ * of |a|, |c| in b); w_bar_0 = w_bar_nk = 0 (those levels do not enter T).
+ *   u: the step's input (domain plus 2-point halo); lam, x: domain;
+ *   w, w_bar: nk+1 staggered levels (w_bar written on all of them);
+ *   coeff_bar: device pointer to one double (FP64 for both dtypes; the
+ *     per-point products are summed in FP64 per 64 x 4 tile, then over the
+ *     tiles in a fixed order, so the result is reproducible).
+ * Either output may be NULL (not both).  coeff_bar needs a device
+ * workspace of stencil_param_workspace_bytes(domain) bytes (8-byte aligned)
+ * for the per-tile sums.  Outputs may not overlap inputs, the workspace or
+ * each other (STENCIL_E_ALIAS). */
+size_t stencil_param_workspace_bytes(stencil_dtype dtype, const int64_t domain[3]);
+int stencil_step_param_adjoint(stencil_dtype dtype, const stencil_field* u, const stencil_field* w,
+                               const stencil_field* x, const stencil_field* lam,
+                               stencil_field* w_bar, double* coeff_bar, const int64_t domain[3],
+                               double dt_dz, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------- batched */
 /* Many independent fields of uneven sizes in one persistent launch (each
  * field is its own stencil call in the sense of Sec. 2.2; the batch only

@@ -109,6 +109,8 @@ SIGNATURES = {
     "stencil_hdiff_adjoint": (I, [I, PF, VP, PF, PI64, D, PO, VP]),
     "stencil_vadv_adjoint": (I, [I, PF, PF, PF, PI64, D, PO, VP]),
     "stencil_step_adjoint": (I, [I, PF, PF, VP, PF, PF, PI64, D, D, PO, VP]),
+    "stencil_param_workspace_bytes": (SZ, [I, PI64]),
+    "stencil_step_param_adjoint": (I, [I, PF, PF, PF, PF, PF, VP, PI64, D, VP, SZ, VP]),
     "stencil_batch_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchItem)]),
     "stencil_batch_adjoint_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchAdjointItem)]),
     "stencil_step_batched": (I, [I, I, ctypes.POINTER(StencilBatchItem), VP, SZ, PO, VP]),

@@ -27,6 +27,7 @@ __all__ = [
     "stencil_version", "stencil_last_error", "stencil_max_fused_nk", "stencil_mask_bytes",
     "stencil_workspace_bytes", "stencil_hdiff", "stencil_vadv", "stencil_step",
     "stencil_hdiff_adjoint", "stencil_vadv_adjoint", "stencil_step_adjoint",
+    "stencil_param_workspace_bytes", "stencil_step_param_adjoint",
     "stencil_batch_workspace_bytes", "stencil_batch_adjoint_workspace_bytes",
     "stencil_step_batched", "stencil_step_adjoint_batched", "stencil_graph_capture_steps",
     "stencil_graph_launch", "stencil_graph_destroy", "stencil_autotune", "stencil_tuning_lookup",
@@ -180,6 +181,21 @@ def stencil_step_adjoint(x_bar, w, mask, u_bar, data_bar, domain, coeff, dt_dz, 
     _lib.check(_lib.lib().stencil_step_adjoint(_dt(dtype, x_bar, u_bar), _fld(x_bar), _fld(w), _ptr(mask),
                                                _fld(u_bar), _fld(data_bar), _lib.domain3(domain),
                                                float(coeff), float(dt_dz), _opts(opts), _stream(stream)))
+
+
+# ------------------------------------------------------------------ parameter gradients
+def stencil_param_workspace_bytes(dtype, domain) -> int:
+    return _lib.lib().stencil_param_workspace_bytes(_dt(dtype), _lib.domain3(domain))
+
+
+def stencil_step_param_adjoint(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, ws=None, stream=None,
+                               dtype=None):
+    """coeff_bar: a device tensor holding one float64 (or None); w_bar: a
+    staggered field (or None); ws: the workspace tensor for coeff_bar."""
+    nb = 0 if ws is None else ws.numel() * ws.element_size()
+    _lib.check(_lib.lib().stencil_step_param_adjoint(
+        _dt(dtype, lam), _fld(u), _fld(w), _fld(x), _fld(lam), _fld(w_bar), _ptr(coeff_bar),
+        _lib.domain3(domain), float(dt_dz), _ptr(ws), nb, _stream(stream)))
 
 
 # ------------------------------------------------------------------ batched

@@ -4,10 +4,11 @@ limiter mask), the backward calls the hand-written adjoint kernels.
 Tensors use the canonical contiguous layouts (k, j, i):
   u       (nk, nj+4, ni+4)  -- domain plus its 2-point halo
   data    (nk, nj, ni)
-  w       (nk+1, nj, ni)    -- staggered levels; not differentiated
-Outputs are the new interior values (nk, nj, ni).  Gradients flow to u (over
-its halo as well) and to data; the step is differentiated almost everywhere,
-with the limiter decisions of the forward pass held fixed.
+  w       (nk+1, nj, ni)    -- staggered levels
+Outputs are the new interior values (nk, nj, ni).  Gradients of the step
+flow to u (over its halo as well), data, w and a tensor coeff; the step is
+differentiated almost everywhere, with the limiter decisions of the forward
+pass held fixed (and d|t|/dt = 0 at t = 0 in the diagonal of T).
 """
 from __future__ import annotations
 
@@ -28,30 +29,48 @@ def _dims(data: torch.Tensor):
 
 
 class StencilStep(torch.autograd.Function):
-    """x = vadv(hdiff(u), data, w): one fused time step."""
+    """x = vadv(hdiff(u), data, w): one fused time step.  coeff may be a
+    float or a 0-d tensor; gradients flow to u, data, w and a tensor coeff."""
 
     @staticmethod
-    def forward(ctx, u, data, w, coeff: float, dt_dz: float):
+    def forward(ctx, u, data, w, coeff, dt_dz: float):
         u, data, w = u.contiguous(), data.contiguous(), w.contiguous()
         ni, nj, nk = _dims(data)
         dom = (ni, nj, nk)
+        c = float(coeff)
         out = torch.empty_like(data)
         mask = torch.empty(max(api.stencil_mask_bytes(dom), 1), dtype=torch.uint8, device=u.device)
-        api.stencil_step(_f(u, HALO), _f(data, 0), _f(w, 0), _f(out, 0), dom, coeff, dt_dz, mask=mask)
-        ctx.save_for_backward(w, mask)
-        ctx.coeff, ctx.dt_dz, ctx.dom = coeff, dt_dz, dom
+        api.stencil_step(_f(u, HALO), _f(data, 0), _f(w, 0), _f(out, 0), dom, c, dt_dz, mask=mask)
+        ctx.params = ctx.needs_input_grad[2] or (torch.is_tensor(coeff) and ctx.needs_input_grad[3])
+        # the parameter gradients need the step's input and output
+        ctx.save_for_backward(w, mask, u if ctx.params else None, out if ctx.params else None)
+        ctx.coeff, ctx.dt_dz, ctx.dom = c, dt_dz, dom
+        ctx.coeff_tensor = torch.is_tensor(coeff)
         return out
 
     @staticmethod
     def backward(ctx, xbar):
-        w, mask = ctx.saved_tensors
+        w, mask, u, out = ctx.saved_tensors
         ni, nj, nk = ctx.dom
         xbar = xbar.contiguous()
         ubar = torch.empty((nk, nj + 2 * HALO, ni + 2 * HALO), dtype=xbar.dtype, device=xbar.device)
         dbar = torch.empty_like(xbar)
         api.stencil_step_adjoint(_f(xbar, 0), _f(w, 0), mask, _f(ubar, HALO), _f(dbar, 0), ctx.dom, ctx.coeff,
                                  ctx.dt_dz)
-        return ubar, dbar, None, None, None
+        wbar = cbar = None
+        if ctx.params:
+            want_w = ctx.needs_input_grad[2]
+            want_c = ctx.coeff_tensor and ctx.needs_input_grad[3]
+            wb = torch.empty_like(w) if want_w else None
+            cb = torch.zeros(1, dtype=torch.float64, device=xbar.device) if want_c else None
+            n = api.stencil_param_workspace_bytes(xbar.dtype, ctx.dom) if want_c else 0
+            ws = torch.empty(n, dtype=torch.uint8, device=xbar.device) if n else None
+            api.stencil_step_param_adjoint(_f(u, HALO), _f(w, 0), _f(out, 0), _f(dbar, 0),
+                                           _f(wb, 0) if want_w else None, cb, ctx.dom, ctx.dt_dz, ws=ws,
+                                           dtype=xbar.dtype)
+            wbar = wb
+            cbar = cb.reshape(()).to(xbar.dtype) if want_c else None
+        return ubar, dbar, wbar, cbar, None
 
 
 class HDiff(torch.autograd.Function):

@@ -79,6 +79,30 @@ hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total
 template <typename T>
 hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, int tile_i, hipStream_t s);
 
+// parameter gradients of a step (k_param.hip)
+template <typename T>
+struct WGradArgs {
+  const T* w;  // staggered level 0 at domain (0,0)
+  int64_t w_sj, w_sk;
+  const T* x;  // the step's output
+  int64_t x_sj, x_sk;
+  const T* lam;  // T^{-T} x_bar
+  int64_t l_sj, l_sk;
+  T* wbar;  // staggered, nk+1 levels written
+  int64_t b_sj, b_sk;
+  int ni, nj, nk, tiles_i;
+  T q;  // dt_dz / 4
+};
+// per-tile partial sums of the coeff gradient: one double per 64 x 4 tile
+inline size_t coeff_partial_count(int64_t ni, int64_t nj) {
+  return (size_t)((ni + 63) / 64) * (size_t)((nj + 3) / 4);
+}
+// A: u (halo) and lam in the data slot; W may be NULL (no w_bar);
+// coeff_bar may be NULL (no reduction; partial unused)
+template <typename T>
+hipError_t launch_param_grads(const StepArgs<T>& A, const WGradArgs<T>* W, double* partial, double* coeff_bar,
+                              hipStream_t s);
+
 // fill a strided box with a deterministic pattern (autotuner scratch)
 template <typename T>
 hipError_t launch_fill_pattern(T* p, int64_t n, T lo, T hi, uint32_t seed, hipStream_t s);

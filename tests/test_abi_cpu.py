@@ -343,3 +343,29 @@ def test_batch_adjoint_workspace_and_validation(L):
     arr[1].mask = fw[1].out.data
     arr[1].u_bar = fld(20, 9, 30, base=fw[0].u.data)  # two items writing one buffer
     assert L.stencil_step_adjoint_batched(1, 2, arr, ws, need, None, None) == code("STENCIL_E_ALIAS")
+
+
+def test_param_adjoint_validation(L):
+    b = ctypes.byref
+    u, data, w, out, d = fields(16, 12, 8)
+    lam = fld(16, 12, 8, halo=0, base=BASE + (5 << 32))
+    x = fld(16, 12, 8, halo=0, base=BASE + (6 << 32))
+    wb = fld(16, 12, 8, halo=0, kextra=1, base=BASE + (7 << 32))
+    cb = BASE + (8 << 32)
+    ws = BASE + (9 << 32)
+    need = L.stencil_param_workspace_bytes(1, d)
+    assert need >= 8 * 1 * 3 and need % 256 == 0  # one double per 64 x 4 tile
+    call = lambda wbar=b(wb), coeff_bar=cb, ws=ws, nb=need: L.stencil_step_param_adjoint(  # noqa: E731
+        1, b(u), b(w), b(x), b(lam), wbar, coeff_bar, d, 0.5, ws, nb, None)
+    assert call(wbar=None, coeff_bar=None) == code("STENCIL_E_NULL")
+    assert call(ws=None) == code("STENCIL_E_WORKSPACE")
+    assert call(nb=need - 8) == code("STENCIL_E_WORKSPACE")
+    assert call(coeff_bar=cb + 4) == code("STENCIL_E_DTYPE")
+    assert call(coeff_bar=lam.data) == code("STENCIL_E_ALIAS")  # output inside an input
+    assert call(ws=x.data) == code("STENCIL_E_ALIAS")
+    wb2 = fld(16, 12, 8, halo=0, kextra=1, base=x.data)
+    assert call(wbar=b(wb2)) == code("STENCIL_E_ALIAS")
+    short = fld(16, 12, 8, halo=0, base=BASE + (7 << 32))  # nk levels, w_bar needs nk + 1
+    assert call(wbar=b(short)) == code("STENCIL_E_SHAPE")
+    # w_bar alone needs no workspace
+    assert L.stencil_param_workspace_bytes(1, _lib.domain3((0, 12, 8))) == 0
