@@ -397,6 +397,23 @@ void oracle_laplacian(int ni, int nj, int nk, const double* u, double* lap) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Periodic boundaries: the 2-point halo of a padded field holds the     */
+/* interior values at the wrapped indices (i mod ni, j mod nj), corners  */
+/* included.  In place on a padded [nk][nj+4][ni+4] array.              */
+/* ------------------------------------------------------------------ */
+static int wrap(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+
+void oracle_halo_periodic(int ni, int nj, int nk, double* u) {
+  if (ni <= 0 || nj <= 0) return;
+  for (int k = 0; k < nk; ++k)
+    for (int j = -2; j < nj + 2; ++j)
+      for (int i = -2; i < ni + 2; ++i) {
+        if (i >= 0 && i < ni && j >= 0 && j < nj) continue;
+        u[UIDX(i, j, k)] = u[UIDX(wrap(i, ni), wrap(j, nj), k)];
+      }
+}
+
+/* ------------------------------------------------------------------ */
 /* Parameter gradients of one step (parameter tuning).                  */
 /* With the limiter decisions held fixed the diffusion is               */
 /*   h = u - coeff * D(u),  D(u)(p) = (Fx(p) - Fx(p-ei)) + (Fy(p) - Fy(p-ej)) */

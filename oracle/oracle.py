@@ -46,8 +46,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
+        # (re)build when missing or older than its source, so a stale
+        # library never answers for the current definitions
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
         L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         bp = ctypes.POINTER(ctypes.c_ubyte)
@@ -66,6 +68,7 @@ def lib():
             "oracle_laplacian": [I, I, I, dp, dp],
             "oracle_hdiff_divergence": [I, I, I, dp, bp, bp, dp],
             "oracle_w_grad": [I, I, I, dp, dp, dp, D, dp],
+            "oracle_halo_periodic": [I, I, I, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -252,3 +255,12 @@ def w_grad(w, x, lam, dt_dz):
     wbar = np.zeros((nk + 1, nj, ni))
     lib().oracle_w_grad(ni, nj, nk, _d(w), _d(x), _d(lam), float(dt_dz), _d(wbar))
     return wbar
+
+
+def halo_periodic(u):
+    """A copy of the padded array u with its 2-point halo filled periodically
+    from the interior (corners included)."""
+    ni, nj, nk = _dims_padded(u)
+    v = _f64(u, (nk, nj + 4, ni + 4)).copy()
+    lib().oracle_halo_periodic(ni, nj, nk, _d(v))
+    return v
