@@ -103,6 +103,15 @@ typedef enum {
                                    take the one-ended solve) */
 } stencil_column_store;
 
+/* Boundary condition of a time step's output (the paper leaves halo
+ * handling to the user; Sec. 2.2 only fixes that a stencil reads its halo). */
+typedef enum {
+  STENCIL_BOUNDARY_FROZEN = 0,  /* the output's halo is not written */
+  STENCIL_BOUNDARY_PERIODIC = 1 /* after the step the output's 2-point halo holds
+                                   the new interior at the wrapped indices
+                                   (i mod ni, j mod nj), corners included */
+} stencil_boundary;
+
 /* Optional per-call options; pass NULL for defaults. */
 typedef struct {
   int32_t impl;         /* stencil_impl */
@@ -111,6 +120,9 @@ typedef struct {
   int32_t column_store; /* stencil_column_store */
   void* workspace;      /* device memory for STENCIL_IMPL_PLAIN temporaries */
   size_t workspace_bytes;
+  int32_t boundary;     /* stencil_boundary of stencil_step (and of the graph
+                           loop, which calls it): PERIODIC needs an output
+                           with the 2-point halo */
 } stencil_options;
 
 typedef enum {
@@ -163,8 +175,9 @@ int stencil_vadv(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
                  double dt_dz, const stencil_options* opts, hipStream_t stream);
 
 /* One time step: out = vadv(hdiff(u), data, w).  Arguments as above; the
- * halo of out is untouched, so ping-pong buffers with equal halos keep a
- * frozen boundary. */
+ * halo of out is untouched (ping-pong buffers with equal halos keep a
+ * frozen boundary) unless opts->boundary is PERIODIC, which then fills it
+ * from the new interior. */
 int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_field* data,
                  const stencil_field* w, stencil_field* out, const int64_t domain[3],
                  double coeff, double dt_dz, void* mask, const stencil_options* opts,
@@ -192,6 +205,13 @@ int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
                          const stencil_field* w, const void* mask, stencil_field* u_bar,
                          stencil_field* data_bar, const int64_t domain[3], double coeff,
                          double dt_dz, const stencil_options* opts, hipStream_t stream);
+
+/* Fill the 2-point halo of `f` (a field with the halo, as u) on `domain`
+ * according to `boundary`: PERIODIC copies the interior at the wrapped
+ * indices, corners included (the single-GPU half of a halo exchange);
+ * FROZEN does nothing.  The interior is not modified. */
+int stencil_halo_update(stencil_dtype dtype, stencil_field* f, const int64_t domain[3], int boundary,
+                        hipStream_t stream);
 
 /* ------------------------------------------------------ parameter gradients */
 /* Gradients of a scalar loss L with respect to the parameters of one step
@@ -226,7 +246,7 @@ int stencil_step_param_adjoint(stencil_dtype dtype, const stencil_field* u, cons
  * it stands for, and additionally no output of one item may overlap any
  * buffer of another (all items run concurrently): STENCIL_E_ALIAS.
  * Limits: n <= 1024 items, nk <= 144 per item (STENCIL_E_UNSUPPORTED), the
- * fused kernels only (impl PLAIN: STENCIL_E_UNSUPPORTED).  Items with an
+ * fused kernels only (impl PLAIN, or a PERIODIC boundary: STENCIL_E_UNSUPPORTED).  Items with an
  * empty domain are skipped (their outputs untouched), except that an
  * adjoint item with nk > 0 and an empty horizontal domain zeroes u_bar as
  * the single-field adjoint does.  The tile is opts->tile_i, else the tuning

@@ -32,6 +32,7 @@ CODES = {v: k for k, v in ERRORS.items()}
 
 IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN = 0, 1, 2
 COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF, COLUMN_SPLIT = 0, 1, 2, 3
+BOUNDARY_FROZEN, BOUNDARY_PERIODIC = 0, 1
 OP_HDIFF, OP_VADV, OP_STEP, OP_HDIFF_ADJOINT, OP_VADV_ADJOINT, OP_STEP_ADJOINT = range(6)
 
 I64x3 = ctypes.c_int64 * 3
@@ -49,6 +50,7 @@ class StencilOptions(ctypes.Structure):
         ("column_store", ctypes.c_int32),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("boundary", ctypes.c_int32),
     ]
 
 
@@ -110,6 +112,7 @@ SIGNATURES = {
     "stencil_vadv_adjoint": (I, [I, PF, PF, PF, PI64, D, PO, VP]),
     "stencil_step_adjoint": (I, [I, PF, PF, VP, PF, PF, PI64, D, D, PO, VP]),
     "stencil_param_workspace_bytes": (SZ, [I, PI64]),
+    "stencil_halo_update": (I, [I, PF, PI64, I, VP]),
     "stencil_step_param_adjoint": (I, [I, PF, PF, PF, PF, PF, VP, PI64, D, VP, SZ, VP]),
     "stencil_batch_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchItem)]),
     "stencil_batch_adjoint_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchAdjointItem)]),

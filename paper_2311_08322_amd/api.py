@@ -16,18 +16,18 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
+from ._lib import (BOUNDARY_FROZEN, BOUNDARY_PERIODIC, COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
                    IMPL_PLAIN, OP_HDIFF, OP_HDIFF_ADJOINT, OP_STEP, OP_STEP_ADJOINT, OP_VADV,
                    OP_VADV_ADJOINT, StencilError)
 
 __all__ = [
     "Field", "Options", "StencilError", "F32", "F64",
-    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
+    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "BOUNDARY_FROZEN", "BOUNDARY_PERIODIC", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
     "OP_HDIFF", "OP_VADV", "OP_STEP", "OP_HDIFF_ADJOINT", "OP_VADV_ADJOINT", "OP_STEP_ADJOINT",
     "stencil_version", "stencil_last_error", "stencil_max_fused_nk", "stencil_mask_bytes",
     "stencil_workspace_bytes", "stencil_hdiff", "stencil_vadv", "stencil_step",
     "stencil_hdiff_adjoint", "stencil_vadv_adjoint", "stencil_step_adjoint",
-    "stencil_param_workspace_bytes", "stencil_step_param_adjoint",
+    "stencil_param_workspace_bytes", "stencil_step_param_adjoint", "stencil_halo_update",
     "stencil_batch_workspace_bytes", "stencil_batch_adjoint_workspace_bytes",
     "stencil_step_batched", "stencil_step_adjoint_batched", "stencil_graph_capture_steps",
     "stencil_graph_launch", "stencil_graph_destroy", "stencil_autotune", "stencil_tuning_lookup",
@@ -63,6 +63,7 @@ class Options:
     tile_j: int = 0
     column_store: int = COLUMN_AUTO
     workspace: Optional[torch.Tensor] = None
+    boundary: int = BOUNDARY_FROZEN
 
     def c(self) -> _lib.StencilOptions:
         o = _lib.StencilOptions()
@@ -73,6 +74,7 @@ class Options:
         if self.workspace is not None:
             o.workspace = self.workspace.data_ptr()
             o.workspace_bytes = self.workspace.numel() * self.workspace.element_size()
+        o.boundary = self.boundary
         return o
 
 
@@ -181,6 +183,11 @@ def stencil_step_adjoint(x_bar, w, mask, u_bar, data_bar, domain, coeff, dt_dz, 
     _lib.check(_lib.lib().stencil_step_adjoint(_dt(dtype, x_bar, u_bar), _fld(x_bar), _fld(w), _ptr(mask),
                                                _fld(u_bar), _fld(data_bar), _lib.domain3(domain),
                                                float(coeff), float(dt_dz), _opts(opts), _stream(stream)))
+
+
+def stencil_halo_update(f, domain, boundary=BOUNDARY_PERIODIC, stream=None, dtype=None):
+    _lib.check(_lib.lib().stencil_halo_update(_dt(dtype, f), _fld(f), _lib.domain3(domain), int(boundary),
+                                              _stream(stream)))
 
 
 # ------------------------------------------------------------------ parameter gradients

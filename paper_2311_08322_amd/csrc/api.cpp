@@ -167,6 +167,8 @@ int check_opts(const stencil_options* o) {
   if (o->column_store < 0 || o->column_store > STENCIL_COLUMN_SPLIT)
     return fail(STENCIL_E_ARG, "options.column_store = %d unknown", (int)o->column_store);
   if (o->workspace_bytes && !o->workspace) return fail(STENCIL_E_NULL, "options.workspace is NULL");
+  if (o->boundary != STENCIL_BOUNDARY_FROZEN && o->boundary != STENCIL_BOUNDARY_PERIODIC)
+    return fail(STENCIL_E_ARG, "options.boundary = %d unknown", (int)o->boundary);
   return STENCIL_OK;
 }
 
@@ -414,7 +416,8 @@ int stencil_vadv(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
   TRY(check_field("u", u, domain, ROLE_INTERIOR, es));
   TRY(check_field("data", data, domain, ROLE_INTERIOR, es));
   TRY(check_field("w", w, domain, ROLE_STAGGERED, es));
-  TRY(check_field("out", out, domain, ROLE_INTERIOR, es));
+  const bool periodic = opts && opts->boundary == STENCIL_BOUNDARY_PERIODIC;
+  TRY(check_field("out", out, domain, periodic ? ROLE_HALO : ROLE_INTERIOR, es));
   const Span so = span_of(out, es);
   TRY(check_no_alias("out", so, "u", span_of(u, es)));
   TRY(check_no_alias("out", so, "data", span_of(data, es)));
@@ -438,7 +441,8 @@ int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
   TRY(check_field("u", u, domain, ROLE_HALO, es));
   TRY(check_field("data", data, domain, ROLE_INTERIOR, es));
   TRY(check_field("w", w, domain, ROLE_STAGGERED, es));
-  TRY(check_field("out", out, domain, ROLE_INTERIOR, es));
+  const bool periodic = opts && opts->boundary == STENCIL_BOUNDARY_PERIODIC;
+  TRY(check_field("out", out, domain, periodic ? ROLE_HALO : ROLE_INTERIOR, es));
   const Span so = span_of(out, es);
   TRY(check_no_alias("out", so, "u", span_of(u, es)));
   TRY(check_no_alias("out", so, "data", span_of(data, es)));
@@ -455,9 +459,25 @@ int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
   TRY(fused_nk_ok(r, domain));
   if (r.impl == STENCIL_IMPL_PLAIN) TRY(need_plain_ws(r, plain_ws_bytes(es, domain)));
   TRY(check_device());
-  return dtype == STENCIL_F64
-             ? run_step<double>(u, data, w, out, domain, coeff, dt_dz, mask, r, stream)
-             : run_step<float>(u, data, w, out, domain, coeff, dt_dz, mask, r, stream);
+  TRY(dtype == STENCIL_F64 ? run_step<double>(u, data, w, out, domain, coeff, dt_dz, mask, r, stream)
+                           : run_step<float>(u, data, w, out, domain, coeff, dt_dz, mask, r, stream));
+  return periodic ? stencil_halo_update(dtype, out, domain, STENCIL_BOUNDARY_PERIODIC, stream) : ok();
+}
+
+int stencil_halo_update(stencil_dtype dtype, stencil_field* f, const int64_t domain[3], int boundary,
+                        hipStream_t stream) {
+  TRY(check_dtype(dtype));
+  TRY(check_domain(domain));
+  if (boundary != STENCIL_BOUNDARY_FROZEN && boundary != STENCIL_BOUNDARY_PERIODIC)
+    return fail(STENCIL_E_ARG, "boundary = %d unknown", boundary);
+  TRY(check_field("f", f, domain, ROLE_HALO, esize(dtype)));
+  if (boundary == STENCIL_BOUNDARY_FROZEN || domain_empty(domain)) return ok();
+  TRY(check_device());
+  const int ni = (int)domain[0], nj = (int)domain[1], nk = (int)domain[2];
+  hipError_t e = dtype == STENCIL_F64
+                     ? launch_halo_periodic<double>(at_origin_mut<double>(f), f->stride[1], f->stride[2], ni, nj, nk, stream)
+                     : launch_halo_periodic<float>(at_origin_mut<float>(f), f->stride[1], f->stride[2], ni, nj, nk, stream);
+  return hip_status(e, "periodic halo update");
 }
 
 int stencil_hdiff_adjoint(stencil_dtype dtype, const stencil_field* out_bar, const void* mask,

@@ -64,6 +64,8 @@ int check_batch_args(stencil_dtype dtype, int n, const void* items, const stenci
   TRY(check_opts(opts));
   if (opts && opts->impl == STENCIL_IMPL_PLAIN)
     return fail(STENCIL_E_UNSUPPORTED, "the batched launch runs the fused kernels only");
+  if (opts && opts->boundary != STENCIL_BOUNDARY_FROZEN)
+    return fail(STENCIL_E_UNSUPPORTED, "the batched launch leaves halos frozen (use stencil_halo_update)");
   return STENCIL_OK;
 }
 

@@ -103,6 +103,10 @@ template <typename T>
 hipError_t launch_param_grads(const StepArgs<T>& A, const WGradArgs<T>* W, double* partial, double* coeff_bar,
                               hipStream_t s);
 
+// periodic halo fill of a padded field (p at domain (0,0,0); k_halo.hip)
+template <typename T>
+hipError_t launch_halo_periodic(T* p, int64_t sj, int64_t sk, int ni, int nj, int nk, hipStream_t s);
+
 // fill a strided box with a deterministic pattern (autotuner scratch)
 template <typename T>
 hipError_t launch_fill_pattern(T* p, int64_t n, T lo, T hi, uint32_t seed, hipStream_t s);

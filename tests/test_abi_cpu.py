@@ -369,3 +369,21 @@ def test_param_adjoint_validation(L):
     assert call(wbar=b(short)) == code("STENCIL_E_SHAPE")
     # w_bar alone needs no workspace
     assert L.stencil_param_workspace_bytes(1, _lib.domain3((0, 12, 8))) == 0
+
+
+def test_boundary_option_and_halo_update_validation(L):
+    u, data, w, out, d = fields()
+    o = _lib.StencilOptions()
+    o.boundary = 7
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    o.boundary = _lib.BOUNDARY_PERIODIC
+    out0 = fld(16, 12, 8, halo=0, base=out.data)  # a periodic step writes out's halo
+    assert step(L, u, data, w, out0, d, opts=o) == code("STENCIL_E_HALO")
+    b = ctypes.byref
+    assert L.stencil_halo_update(1, b(out0), d, 1, None) == code("STENCIL_E_HALO")
+    assert L.stencil_halo_update(1, b(u), d, 5, None) == code("STENCIL_E_ARG")
+    assert L.stencil_halo_update(1, b(u), d, 0, None) == 0  # frozen: nothing to do
+    assert L.stencil_halo_update(1, b(u), _lib.domain3((0, 12, 8)), 1, None) == 0
+    items = batch_items([(16, 12, 8)])
+    assert L.stencil_step_batched(1, 1, items, BASE + (64 << 32), 1 << 20, b(o), None) == code(
+        "STENCIL_E_UNSUPPORTED")
