@@ -105,11 +105,11 @@ __global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const 
     const int tile = w - h->prefix()[e];
     if constexpr (sizeof(T) == 8) {
       if (A.nk <= 96)
-        column_split_tile<T, 48, GT4MI_PD, true, 1>(A, tile, xch);
+        column_split_tile<T, 48, GT4MI_COL_PD, true, 1>(A, tile, xch);
       else
-        column_split_tile<T, 72, GT4MI_PD, true, 2>(A, tile, xch);
+        column_split_tile<T, 72, GT4MI_COL_PD, true, 2>(A, tile, xch);
     } else {
-      column_split_tile<T, 72, GT4MI_PD, true, 1>(A, tile, xch);
+      column_split_tile<T, 72, GT4MI_COL_PD, true, 1>(A, tile, xch);
     }
     __syncthreads();
   }

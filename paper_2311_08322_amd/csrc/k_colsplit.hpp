@@ -13,6 +13,12 @@
 
 #include "k_step.hpp"
 
+// Levels loaded ahead by the column-only kernels (two loads per level, so
+// they can run further ahead than the fused step at the same registers).
+#ifndef GT4MI_COL_PD
+#define GT4MI_COL_PD 2
+#endif
+
 namespace gt4mi {
 
 // COL = 1: e and f of every level in VGPRs; COL = 2: f staged in `out`.
@@ -111,7 +117,13 @@ __global__ void __launch_bounds__(2 * kWG) k_column_split(StepArgs<T> A) {
 
 // FP64 keeps e and f of both halves in VGPRs up to 96 levels, then stages f
 // in the output up to 144; FP32 keeps both up to 160.
-constexpr int kColsplitRegNkF64 = 96;
+#ifndef GT4MI_COLSPLIT_REG_NK_F64
+#define GT4MI_COLSPLIT_REG_NK_F64 96
+#endif
+#ifndef GT4MI_COLSPLIT_STAGED_CLASSES
+#define GT4MI_COLSPLIT_STAGED_CLASSES(X) X(72)
+#endif
+constexpr int kColsplitRegNkF64 = GT4MI_COLSPLIT_REG_NK_F64;
 constexpr int kColsplitStagedNkhF64 = 72;
 
 template <typename T>
@@ -128,17 +140,20 @@ hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s) {
 #define GT4MI_COLSPLIT_CASE(N)                                                                 \
   if constexpr (2 * N <= (sizeof(T) == 8 ? kColsplitRegNkF64 : 160)) {                         \
     if (nkh <= N) {                                                                            \
-      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_PD, ADJ, 1>), grid, block, 0, s, A);     \
+      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_COL_PD, ADJ, 1>), grid, block, 0, s, A);     \
       return hipGetLastError();                                                                \
     }                                                                                          \
   }
   GT4MI_COLSPLIT_CASE(16) GT4MI_COLSPLIT_CASE(24) GT4MI_COLSPLIT_CASE(48) GT4MI_COLSPLIT_CASE(80)
 #undef GT4MI_COLSPLIT_CASE
   if constexpr (sizeof(T) == 8) {
-    if (nkh <= kColsplitStagedNkhF64) {
-      hipLaunchKernelGGL((k_column_split<T, kColsplitStagedNkhF64, GT4MI_PD, ADJ, 2>), grid, block, 0, s, A);
-      return hipGetLastError();
+#define GT4MI_COLSPLIT_STAGED(N)                                                                 \
+    if (nkh <= N) {                                                                              \
+      hipLaunchKernelGGL((k_column_split<T, N, GT4MI_COL_PD, ADJ, 2>), grid, block, 0, s, A);    \
+      return hipGetLastError();                                                                  \
     }
+    GT4MI_COLSPLIT_STAGED_CLASSES(GT4MI_COLSPLIT_STAGED)
+#undef GT4MI_COLSPLIT_STAGED
   }
   return hipErrorInvalidValue;
 }
