@@ -27,6 +27,13 @@
  *       a_0 = c_{nk-1} = 0,  b_k = 1 + |a_k| + |c_k|,  d_k = u_k + data_k,
  *     solved by the Thomas algorithm (FORWARD elimination, BACKWARD
  *     substitution).
+ *   - Two generalisations of the diffusion, parity unaffected for the
+ *     stated form: a per-point coefficient kappa(i,j,k) in place of the
+ *     scalar coeff in the update, and a damping form whose Laplacian stage
+ *     is the discrete Laplacian itself (the negative of the stated lap),
+ *     every later stage unchanged.  With every flux kept the stated form
+ *     adds coeff times the squared discrete Laplacian, the damping form
+ *     subtracts it (fourth-order diffusion).
  *
  * Array conventions (C order, all strides implied by the sizes):
  *   padded  u, out, ubar : [nk][nj+4][ni+4], U(i,j,k) = u[k][j+2][i+2],
@@ -68,34 +75,41 @@
 static int limiter_keeps(double f, double g) { return !(f * g > 0.0); }
 static int limiter_keeps_f32(float f, float g) { return !(f * g > 0.0f); }
 
-/* Laplacian stage, fixed association: 4u - ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])). */
-static double lap64(const double* u, int ni, int nj, int i, int j, int k) {
+/* Laplacian stage, fixed association.  The stated form takes
+ * 4u - ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])), the negative of the discrete
+ * Laplacian; the damping form (`damping` != 0) takes the discrete Laplacian
+ * itself, ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])) - 4u, with every later stage
+ * unchanged, so that with every flux kept the update is u - coeff * (discrete
+ * Laplacian applied twice): fourth-order damping. */
+static double lap64(const double* u, int ni, int nj, int i, int j, int k, int damping) {
   double s = (u[UIDX(i - 1, j, k)] + u[UIDX(i + 1, j, k)]) +
              (u[UIDX(i, j - 1, k)] + u[UIDX(i, j + 1, k)]);
-  return 4.0 * u[UIDX(i, j, k)] - s;
+  double c = 4.0 * u[UIDX(i, j, k)];
+  return damping ? s - c : c - s;
 }
-static float lap32(const double* u, int ni, int nj, int i, int j, int k) {
+static float lap32(const double* u, int ni, int nj, int i, int j, int k, int damping) {
   float s = ((float)u[UIDX(i - 1, j, k)] + (float)u[UIDX(i + 1, j, k)]) +
             ((float)u[UIDX(i, j - 1, k)] + (float)u[UIDX(i, j + 1, k)]);
-  return 4.0f * (float)u[UIDX(i, j, k)] - s;
+  float c = 4.0f * (float)u[UIDX(i, j, k)];
+  return damping ? s - c : c - s;
 }
 
 /* ------------------------------------------------------------------ */
 /* Limiter masks of the horizontal diffusion (Sec. 3.1 benchmark)        */
 /* ------------------------------------------------------------------ */
-void oracle_hdiff_masks(int ni, int nj, int nk, const double* u, int decide_f32,
-                        unsigned char* mx, unsigned char* my) {
+void oracle_hdiff_masks_form(int ni, int nj, int nk, const double* u, int decide_f32, int damping,
+                             unsigned char* mx, unsigned char* my) {
   for (int k = 0; k < nk; ++k) {
     /* x-fluxes on [-1, ni) x [0, nj) */
     for (int j = 0; j < nj; ++j)
       for (int i = -1; i < ni; ++i) {
         int keep;
         if (decide_f32) {
-          float f = lap32(u, ni, nj, i + 1, j, k) - lap32(u, ni, nj, i, j, k);
+          float f = lap32(u, ni, nj, i + 1, j, k, damping) - lap32(u, ni, nj, i, j, k, damping);
           float g = (float)u[UIDX(i + 1, j, k)] - (float)u[UIDX(i, j, k)];
           keep = limiter_keeps_f32(f, g);
         } else {
-          double f = lap64(u, ni, nj, i + 1, j, k) - lap64(u, ni, nj, i, j, k);
+          double f = lap64(u, ni, nj, i + 1, j, k, damping) - lap64(u, ni, nj, i, j, k, damping);
           double g = u[UIDX(i + 1, j, k)] - u[UIDX(i, j, k)];
           keep = limiter_keeps(f, g);
         }
@@ -106,17 +120,22 @@ void oracle_hdiff_masks(int ni, int nj, int nk, const double* u, int decide_f32,
       for (int i = 0; i < ni; ++i) {
         int keep;
         if (decide_f32) {
-          float f = lap32(u, ni, nj, i, j + 1, k) - lap32(u, ni, nj, i, j, k);
+          float f = lap32(u, ni, nj, i, j + 1, k, damping) - lap32(u, ni, nj, i, j, k, damping);
           float g = (float)u[UIDX(i, j + 1, k)] - (float)u[UIDX(i, j, k)];
           keep = limiter_keeps_f32(f, g);
         } else {
-          double f = lap64(u, ni, nj, i, j + 1, k) - lap64(u, ni, nj, i, j, k);
+          double f = lap64(u, ni, nj, i, j + 1, k, damping) - lap64(u, ni, nj, i, j, k, damping);
           double g = u[UIDX(i, j + 1, k)] - u[UIDX(i, j, k)];
           keep = limiter_keeps(f, g);
         }
         my[MYIDX(i, j, k)] = (unsigned char)keep;
       }
   }
+}
+
+void oracle_hdiff_masks(int ni, int nj, int nk, const double* u, int decide_f32,
+                        unsigned char* mx, unsigned char* my) {
+  oracle_hdiff_masks_form(ni, nj, nk, u, decide_f32, 0, mx, my);
 }
 
 /* ------------------------------------------------------------------ */
@@ -127,9 +146,13 @@ void oracle_hdiff_masks(int ni, int nj, int nk, const double* u, int decide_f32,
 /* masks held fixed it is its (a.e.) tangent-linear map.                */
 /* Writes the interior of `out` only (out[k][j][i], interior layout).   */
 /* ------------------------------------------------------------------ */
+/* The coefficient of the update at interior point (i,j,k): the scalar
+ * coeff, or the per-point field kappa (interior layout) when given. */
+#define COEF(i, j, k) (kappa ? kappa[IIDX(i, j, k)] : coeff)
+
 static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coeff,
-                             const unsigned char* mx, const unsigned char* my,
-                             double* out_interior) {
+                             const double* kappa, int damping, const unsigned char* mx,
+                             const unsigned char* my, double* out_interior) {
   const int li = ni + 2, lj = nj + 2; /* lap on the box [-1,ni] x [-1,nj] */
   double* lap = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
   double* fx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)nj);
@@ -139,7 +162,7 @@ static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coe
 #define FY(i, j) fy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)]
   for (int k = 0; k < nk; ++k) {
     for (int j = -1; j <= nj; ++j)
-      for (int i = -1; i <= ni; ++i) LAP(i, j) = lap64(u, ni, nj, i, j, k);
+      for (int i = -1; i <= ni; ++i) LAP(i, j) = lap64(u, ni, nj, i, j, k, damping);
     for (int j = 0; j < nj; ++j)
       for (int i = -1; i < ni; ++i) {
         double f = LAP(i + 1, j) - LAP(i, j);
@@ -153,7 +176,7 @@ static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coe
     for (int j = 0; j < nj; ++j)
       for (int i = 0; i < ni; ++i) {
         double div = (FX(i, j) - FX(i - 1, j)) + (FY(i, j) - FY(i, j - 1));
-        out_interior[IIDX(i, j, k)] = u[UIDX(i, j, k)] - coeff * div;
+        out_interior[IIDX(i, j, k)] = u[UIDX(i, j, k)] - COEF(i, j, k) * div;
       }
   }
 #undef LAP
@@ -164,18 +187,27 @@ static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coe
   free(fy);
 }
 
-/* Forward horizontal diffusion.  `out` is padded: interior = the update,
- * halo = a copy of u's halo (the halo is never computed, only carried). */
-void oracle_hdiff(int ni, int nj, int nk, const double* u, double coeff, int decide_f32,
-                  double* out, unsigned char* mx, unsigned char* my) {
-  oracle_hdiff_masks(ni, nj, nk, u, decide_f32, mx, my);
+/* Forward horizontal diffusion, general form: per-point coefficient kappa
+ * (NULL: the scalar coeff) and the damping form of the Laplacian.  `out` is
+ * padded: interior = the update, halo = a copy of u's halo (the halo is
+ * never computed, only carried). */
+void oracle_hdiff_gen(int ni, int nj, int nk, const double* u, double coeff, const double* kappa,
+                      int damping, int decide_f32, double* out, unsigned char* mx,
+                      unsigned char* my) {
+  oracle_hdiff_masks_form(ni, nj, nk, u, decide_f32, damping, mx, my);
   double* h = (double*)malloc(sizeof(double) * (size_t)ni * (size_t)nj * (size_t)nk + 8);
-  hdiff_with_masks(ni, nj, nk, u, coeff, mx, my, h);
+  hdiff_with_masks(ni, nj, nk, u, coeff, kappa, damping, mx, my, h);
   memcpy(out, u, sizeof(double) * (size_t)(ni + 4) * (size_t)(nj + 4) * (size_t)nk);
   for (int k = 0; k < nk; ++k)
     for (int j = 0; j < nj; ++j)
       for (int i = 0; i < ni; ++i) out[UIDX(i, j, k)] = h[IIDX(i, j, k)];
   free(h);
+}
+
+/* The stated form with a scalar coefficient. */
+void oracle_hdiff(int ni, int nj, int nk, const double* u, double coeff, int decide_f32,
+                  double* out, unsigned char* mx, unsigned char* my) {
+  oracle_hdiff_gen(ni, nj, nk, u, coeff, NULL, 0, decide_f32, out, mx, my);
 }
 
 /* ------------------------------------------------------------------ */
@@ -231,19 +263,19 @@ void oracle_vadv(int ni, int nj, int nk, const double* uin, const double* data, 
   free(d);
 }
 
-/* One time step: horizontal diffusion, then vertical advection with the
- * diffused field as u_k in d_k = u_k + data_k.  `next` is padded: interior
- * = x, halo = u's halo (held fixed). */
-void oracle_step(int ni, int nj, int nk, const double* u, const double* data, const double* w,
-                 double coeff, double dt_dz, int decide_f32, double* next, unsigned char* mx,
-                 unsigned char* my) {
+/* One time step: horizontal diffusion (general form), then vertical
+ * advection with the diffused field as u_k in d_k = u_k + data_k.  `next` is
+ * padded: interior = x, halo = u's halo (held fixed). */
+void oracle_step_gen(int ni, int nj, int nk, const double* u, const double* data, const double* w,
+                     double coeff, const double* kappa, int damping, double dt_dz, int decide_f32,
+                     double* next, unsigned char* mx, unsigned char* my) {
   size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
   memcpy(next, u, sizeof(double) * (size_t)(ni + 4) * (size_t)(nj + 4) * (size_t)nk);
   if (n == 0) return;
-  oracle_hdiff_masks(ni, nj, nk, u, decide_f32, mx, my);
+  oracle_hdiff_masks_form(ni, nj, nk, u, decide_f32, damping, mx, my);
   double* h = (double*)malloc(sizeof(double) * n);
   double* x = (double*)malloc(sizeof(double) * n);
-  hdiff_with_masks(ni, nj, nk, u, coeff, mx, my, h);
+  hdiff_with_masks(ni, nj, nk, u, coeff, kappa, damping, mx, my, h);
   for (size_t p = 0; p < n; ++p) h[p] += data[p];
   thomas_columns(ni, nj, nk, h, w, dt_dz, x);
   for (int k = 0; k < nk; ++k)
@@ -253,34 +285,45 @@ void oracle_step(int ni, int nj, int nk, const double* u, const double* data, co
   free(x);
 }
 
+void oracle_step(int ni, int nj, int nk, const double* u, const double* data, const double* w,
+                 double coeff, double dt_dz, int decide_f32, double* next, unsigned char* mx,
+                 unsigned char* my) {
+  oracle_step_gen(ni, nj, nk, u, data, w, coeff, NULL, 0, dt_dz, decide_f32, next, mx, my);
+}
+
 /* ------------------------------------------------------------------ */
 /* Adjoints (transpose of the a.e. Jacobian, limiter masks held fixed)  */
 /* ------------------------------------------------------------------ */
 
 /* Horizontal diffusion adjoint: ubar = J_h^T lam over the whole padded
- * domain.  lam is given on the interior and is zero outside it. */
-void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsigned char* mx,
-                          const unsigned char* my, double coeff, double* ubar) {
+ * domain, general form.  lam is given on the interior and is zero outside
+ * it. */
+void oracle_hdiff_adjoint_gen(int ni, int nj, int nk, const double* lam, const unsigned char* mx,
+                              const unsigned char* my, double coeff, const double* kappa,
+                              int damping, double* ubar) {
   const int li = ni + 2, lj = nj + 2;
   double* gx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)(nj > 0 ? nj : 1));
   double* gy = (double*)malloc(sizeof(double) * (size_t)(ni > 0 ? ni : 1) * (size_t)(nj + 1));
   double* lb = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
-#define LAM(i, j) (((i) >= 0 && (i) < ni && (j) >= 0 && (j) < nj) ? lam[IIDX(i, j, k)] : 0.0)
+#define INI(i, j) ((i) >= 0 && (i) < ni && (j) >= 0 && (j) < nj)
+#define LAM(i, j) (INI(i, j) ? lam[IIDX(i, j, k)] : 0.0)
+#define MU(i, j) (INI(i, j) ? kappa[IIDX(i, j, k)] * lam[IIDX(i, j, k)] : 0.0)
 #define GX(i, j) ((((i) >= -1 && (i) < ni && (j) >= 0 && (j) < nj)) ? gx[(size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1)] : 0.0)
 #define GY(i, j) ((((i) >= 0 && (i) < ni && (j) >= -1 && (j) < nj)) ? gy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)] : 0.0)
 #define LB(i, j) ((((i) >= -1 && (i) <= ni && (j) >= -1 && (j) <= nj)) ? lb[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)] : 0.0)
   for (int k = 0; k < nk; ++k) {
-    /* out(p) = u(p) - coeff * (Fx(p) - Fx(p-ei) + Fy(p) - Fy(p-ej)):
-     * dout(p)/dFx(q) = -coeff if q == p, +coeff if q == p - ei.
+    /* out(p) = u(p) - coeff(p) * (Fx(p) - Fx(p-ei) + Fy(p) - Fy(p-ej)):
+     * dout(p)/dFx(q) = -coeff(p) if q == p, +coeff(p) if q == p - ei, so
+     * Fx(q) collects -(coeff lam)(q) + (coeff lam)(q+ei).
      * Fx(q) = MX(q) * (lap(q+ei) - lap(q)). Keep the masked flux cotangent. */
     for (int j = 0; j < nj; ++j)
       for (int i = -1; i < ni; ++i) {
-        double fbar = -coeff * (LAM(i, j) - LAM(i + 1, j));
+        double fbar = kappa ? -(MU(i, j) - MU(i + 1, j)) : -coeff * (LAM(i, j) - LAM(i + 1, j));
         gx[(size_t)j * (size_t)(ni + 1) + (size_t)(i + 1)] = mx[MXIDX(i, j, k)] ? fbar : 0.0;
       }
     for (int j = -1; j < nj; ++j)
       for (int i = 0; i < ni; ++i) {
-        double fbar = -coeff * (LAM(i, j) - LAM(i, j + 1));
+        double fbar = kappa ? -(MU(i, j) - MU(i, j + 1)) : -coeff * (LAM(i, j) - LAM(i, j + 1));
         gy[(size_t)(j + 1) * (size_t)ni + (size_t)i] = my[MYIDX(i, j, k)] ? fbar : 0.0;
       }
     /* lap(q) enters Fx(q-ei) with +1 and Fx(q) with -1 (same for y). */
@@ -288,21 +331,31 @@ void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsig
       for (int i = -1; i <= ni; ++i)
         lb[(size_t)(j + 1) * (size_t)li + (size_t)(i + 1)] =
             (GX(i - 1, j) - GX(i, j)) + (GY(i, j - 1) - GY(i, j));
-    /* lap(q) = 4u(q) - u(q+-ei) - u(q+-ej); plus the identity term of out. */
+    /* stated form: lap(q) = 4u(q) - u(q+-ei) - u(q+-ej); the damping form
+     * is its negative.  Plus the identity term of out. */
     for (int j = -2; j < nj + 2; ++j)
       for (int i = -2; i < ni + 2; ++i) {
-        double v = LAM(i, j) + 4.0 * LB(i, j) - LB(i + 1, j) - LB(i - 1, j) - LB(i, j + 1) -
-                   LB(i, j - 1);
+        double nb = LB(i + 1, j) + LB(i - 1, j) + LB(i, j + 1) + LB(i, j - 1);
+        double v = damping ? LAM(i, j) + (nb - 4.0 * LB(i, j))
+                           : LAM(i, j) + 4.0 * LB(i, j) - LB(i + 1, j) - LB(i - 1, j) -
+                                 LB(i, j + 1) - LB(i, j - 1);
         ubar[UIDX(i, j, k)] = v;
       }
   }
+#undef INI
 #undef LAM
+#undef MU
 #undef GX
 #undef GY
 #undef LB
   free(gx);
   free(gy);
   free(lb);
+}
+
+void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsigned char* mx,
+                          const unsigned char* my, double coeff, double* ubar) {
+  oracle_hdiff_adjoint_gen(ni, nj, nk, lam, mx, my, coeff, NULL, 0, ubar);
 }
 
 /* Vertical advection adjoint: lam = T^{-T} xbar.  T^T has sub-diagonal
@@ -339,35 +392,54 @@ void oracle_vadv_adjoint(int ni, int nj, int nk, const double* xbar, const doubl
 }
 
 /* Step adjoint: lam = T^{-T} xbar; ubar = J_h^T lam; databar = lam. */
-void oracle_step_adjoint(int ni, int nj, int nk, const double* xbar, const double* w,
-                         const unsigned char* mx, const unsigned char* my, double coeff,
-                         double dt_dz, double* ubar, double* databar) {
+void oracle_step_adjoint_gen(int ni, int nj, int nk, const double* xbar, const double* w,
+                             const unsigned char* mx, const unsigned char* my, double coeff,
+                             const double* kappa, int damping, double dt_dz, double* ubar,
+                             double* databar) {
   size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
   double* lam = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
   oracle_vadv_adjoint(ni, nj, nk, xbar, w, dt_dz, lam);
-  oracle_hdiff_adjoint(ni, nj, nk, lam, mx, my, coeff, ubar);
+  oracle_hdiff_adjoint_gen(ni, nj, nk, lam, mx, my, coeff, kappa, damping, ubar);
   if (databar) memcpy(databar, lam, sizeof(double) * n);
   free(lam);
 }
 
+void oracle_step_adjoint(int ni, int nj, int nk, const double* xbar, const double* w,
+                         const unsigned char* mx, const unsigned char* my, double coeff,
+                         double dt_dz, double* ubar, double* databar) {
+  oracle_step_adjoint_gen(ni, nj, nk, xbar, w, mx, my, coeff, NULL, 0, dt_dz, ubar, databar);
+}
+
 /* Tangent-linear step with masks held fixed: dx = T^{-1} (J_h v). `v` is
  * padded, `dx` interior.  No forcing term (data enters additively). */
-void oracle_step_tangent(int ni, int nj, int nk, const double* v, const double* w,
-                         const unsigned char* mx, const unsigned char* my, double coeff,
-                         double dt_dz, double* dx) {
+void oracle_step_tangent_gen(int ni, int nj, int nk, const double* v, const double* w,
+                             const unsigned char* mx, const unsigned char* my, double coeff,
+                             const double* kappa, int damping, double dt_dz, double* dx) {
   size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
   if (n == 0) return;
   double* h = (double*)malloc(sizeof(double) * n);
-  hdiff_with_masks(ni, nj, nk, v, coeff, mx, my, h);
+  hdiff_with_masks(ni, nj, nk, v, coeff, kappa, damping, mx, my, h);
   thomas_columns(ni, nj, nk, h, w, dt_dz, dx);
   free(h);
 }
 
+void oracle_step_tangent(int ni, int nj, int nk, const double* v, const double* w,
+                         const unsigned char* mx, const unsigned char* my, double coeff,
+                         double dt_dz, double* dx) {
+  oracle_step_tangent_gen(ni, nj, nk, v, w, mx, my, coeff, NULL, 0, dt_dz, dx);
+}
+
 /* Tangent of the horizontal diffusion alone (interior output). */
+void oracle_hdiff_tangent_gen(int ni, int nj, int nk, const double* v, const unsigned char* mx,
+                              const unsigned char* my, double coeff, const double* kappa,
+                              int damping, double* dh) {
+  if ((size_t)ni * (size_t)nj * (size_t)nk == 0) return;
+  hdiff_with_masks(ni, nj, nk, v, coeff, kappa, damping, mx, my, dh);
+}
+
 void oracle_hdiff_tangent(int ni, int nj, int nk, const double* v, const unsigned char* mx,
                           const unsigned char* my, double coeff, double* dh) {
-  if ((size_t)ni * (size_t)nj * (size_t)nk == 0) return;
-  hdiff_with_masks(ni, nj, nk, v, coeff, mx, my, dh);
+  oracle_hdiff_tangent_gen(ni, nj, nk, v, mx, my, coeff, NULL, 0, dh);
 }
 
 /* Tridiagonal matrix-vector product y = T x per column (for residual pins). */
@@ -393,7 +465,7 @@ void oracle_laplacian(int ni, int nj, int nk, const double* u, double* lap) {
     for (int j = -1; j <= nj; ++j)
       for (int i = -1; i <= ni; ++i)
         lap[(size_t)k * (size_t)(nj + 2) * (size_t)(ni + 2) + (size_t)(j + 1) * (size_t)(ni + 2) +
-            (size_t)(i + 1)] = lap64(u, ni, nj, i, j, k);
+            (size_t)(i + 1)] = lap64(u, ni, nj, i, j, k, 0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -427,9 +499,10 @@ void oracle_halo_periodic(int ni, int nj, int nk, double* u) {
 /*   (d|t|/dt = sign t, taken as 0 at t = 0).                           */
 /* ------------------------------------------------------------------ */
 
-/* D(u) on the interior with the given masks (interior layout). */
-void oracle_hdiff_divergence(int ni, int nj, int nk, const double* u, const unsigned char* mx,
-                             const unsigned char* my, double* div) {
+/* D(u) on the interior with the given masks (interior layout), for the
+ * Laplacian of the given form. */
+void oracle_hdiff_divergence_form(int ni, int nj, int nk, const double* u, const unsigned char* mx,
+                                  const unsigned char* my, int damping, double* div) {
   if ((size_t)ni * (size_t)nj * (size_t)nk == 0) return;
   /* h = u - 1 * D would round; take the flux differences directly */
   const int li = ni + 2, lj = nj + 2;
@@ -437,7 +510,7 @@ void oracle_hdiff_divergence(int ni, int nj, int nk, const double* u, const unsi
 #define LAPD(i, j) lap[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)]
   for (int k = 0; k < nk; ++k) {
     for (int j = -1; j <= nj; ++j)
-      for (int i = -1; i <= ni; ++i) LAPD(i, j) = lap64(u, ni, nj, i, j, k);
+      for (int i = -1; i <= ni; ++i) LAPD(i, j) = lap64(u, ni, nj, i, j, k, damping);
     for (int j = 0; j < nj; ++j)
       for (int i = 0; i < ni; ++i) {
         double fxr = mx[MXIDX(i, j, k)] ? LAPD(i + 1, j) - LAPD(i, j) : 0.0;
@@ -451,14 +524,20 @@ void oracle_hdiff_divergence(int ni, int nj, int nk, const double* u, const unsi
   free(lap);
 }
 
-/* dL/dcoeff = -sum lam * D(u), D with the masks given; the sum is
- * compensated (Neumaier) so that it is accurate to about one rounding. */
-double oracle_coeff_grad(int ni, int nj, int nk, const double* u, const double* lam,
-                         const unsigned char* mx, const unsigned char* my) {
+void oracle_hdiff_divergence(int ni, int nj, int nk, const double* u, const unsigned char* mx,
+                             const unsigned char* my, double* div) {
+  oracle_hdiff_divergence_form(ni, nj, nk, u, mx, my, 0, div);
+}
+
+/* dL/dcoeff = -sum lam * D(u), D with the masks and Laplacian form given;
+ * the sum is compensated (Neumaier) so that it is accurate to about one
+ * rounding. */
+double oracle_coeff_grad_form(int ni, int nj, int nk, const double* u, const double* lam,
+                              const unsigned char* mx, const unsigned char* my, int damping) {
   size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
   if (n == 0) return 0.0;
   double* div = (double*)malloc(sizeof(double) * n);
-  oracle_hdiff_divergence(ni, nj, nk, u, mx, my, div);
+  oracle_hdiff_divergence_form(ni, nj, nk, u, mx, my, damping, div);
   double s = 0.0, comp = 0.0;
   for (size_t p = 0; p < n; ++p) {
     double t = -(lam[p] * div[p]);
@@ -468,6 +547,23 @@ double oracle_coeff_grad(int ni, int nj, int nk, const double* u, const double* 
   }
   free(div);
   return s + comp;
+}
+
+double oracle_coeff_grad(int ni, int nj, int nk, const double* u, const double* lam,
+                         const unsigned char* mx, const unsigned char* my) {
+  return oracle_coeff_grad_form(ni, nj, nk, u, lam, mx, my, 0);
+}
+
+/* Gradient with respect to a per-point coefficient field: out(p) depends on
+ * kappa(p) alone, through -kappa(p) D(u)(p), so dL/dkappa(p) = -lam(p) D(u)(p)
+ * (interior layout). */
+void oracle_coeff_field_grad(int ni, int nj, int nk, const double* u, const double* lam,
+                             const unsigned char* mx, const unsigned char* my, int damping,
+                             double* kbar) {
+  size_t n = (size_t)ni * (size_t)nj * (size_t)nk;
+  if (n == 0) return;
+  oracle_hdiff_divergence_form(ni, nj, nk, u, mx, my, damping, kbar);
+  for (size_t p = 0; p < n; ++p) kbar[p] = -(lam[p] * kbar[p]);
 }
 
 static double sgn(double t) { return t > 0.0 ? 1.0 : (t < 0.0 ? -1.0 : 0.0); }
@@ -497,4 +593,4 @@ void oracle_w_grad(int ni, int nj, int nk, const double* w, const double* x, con
       }
 }
 
-int oracle_version(void) { return 1; }
+int oracle_version(void) { return 2; }

@@ -69,6 +69,15 @@ def lib():
             "oracle_hdiff_divergence": [I, I, I, dp, bp, bp, dp],
             "oracle_w_grad": [I, I, I, dp, dp, dp, D, dp],
             "oracle_halo_periodic": [I, I, I, dp],
+            "oracle_hdiff_masks_form": [I, I, I, dp, I, I, bp, bp],
+            "oracle_hdiff_gen": [I, I, I, dp, D, dp, I, I, dp, bp, bp],
+            "oracle_step_gen": [I, I, I, dp, dp, dp, D, dp, I, D, I, dp, bp, bp],
+            "oracle_hdiff_adjoint_gen": [I, I, I, dp, bp, bp, D, dp, I, dp],
+            "oracle_step_adjoint_gen": [I, I, I, dp, dp, bp, bp, D, dp, I, D, dp, dp],
+            "oracle_step_tangent_gen": [I, I, I, dp, dp, bp, bp, D, dp, I, D, dp],
+            "oracle_hdiff_tangent_gen": [I, I, I, dp, bp, bp, D, dp, I, dp],
+            "oracle_hdiff_divergence_form": [I, I, I, dp, bp, bp, I, dp],
+            "oracle_coeff_field_grad": [I, I, I, dp, dp, bp, bp, I, dp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -76,6 +85,8 @@ def lib():
             fn.restype = None
         L.oracle_coeff_grad.argtypes = [I, I, I, dp, dp, bp, bp]
         L.oracle_coeff_grad.restype = D
+        L.oracle_coeff_grad_form.argtypes = [I, I, I, dp, dp, bp, bp, I]
+        L.oracle_coeff_grad_form.restype = D
         _lib = L
     return _lib
 
@@ -102,28 +113,40 @@ def _u8(a, shape):
     return a
 
 
+def _kappa(kappa, nk, nj, ni):
+    """(array kept alive, pointer): the per-point coefficient field or NULL."""
+    if kappa is None:
+        return None, ctypes.POINTER(ctypes.c_double)()
+    k = _f64(kappa, (nk, nj, ni))
+    return k, _d(k)
+
+
 def _dims_padded(u):
     nk, Nj, Ni = u.shape
     return Ni - 4, Nj - 4, nk
 
 
-def hdiff_masks(u, decide_f32=False):
+def hdiff_masks(u, decide_f32=False, damping=False):
     ni, nj, nk = _dims_padded(u)
     u = _f64(u, (nk, nj + 4, ni + 4))
     mx = np.zeros((nk, nj, ni + 1), np.uint8)
     my = np.zeros((nk, nj + 1, ni), np.uint8)
-    lib().oracle_hdiff_masks(ni, nj, nk, _d(u), int(decide_f32), _b(mx), _b(my))
+    lib().oracle_hdiff_masks_form(ni, nj, nk, _d(u), int(decide_f32), int(damping), _b(mx), _b(my))
     return mx, my
 
 
-def hdiff(u, coeff, decide_f32=False):
-    """Returns (out padded with u's halo, mx, my)."""
+def hdiff(u, coeff, decide_f32=False, kappa=None, damping=False):
+    """Returns (out padded with u's halo, mx, my).  ``kappa`` (interior
+    shape) replaces the scalar coeff by a per-point coefficient; ``damping``
+    takes the discrete Laplacian instead of its negative."""
     ni, nj, nk = _dims_padded(u)
     u = _f64(u, (nk, nj + 4, ni + 4))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     out = np.empty_like(u)
     mx = np.zeros((nk, nj, ni + 1), np.uint8)
     my = np.zeros((nk, nj + 1, ni), np.uint8)
-    lib().oracle_hdiff(ni, nj, nk, _d(u), float(coeff), int(decide_f32), _d(out), _b(mx), _b(my))
+    lib().oracle_hdiff_gen(ni, nj, nk, _d(u), float(coeff), kp, int(damping), int(decide_f32), _d(out),
+                           _b(mx), _b(my))
     return out, mx, my
 
 
@@ -138,27 +161,30 @@ def vadv(uin, data, w, dt_dz):
     return x
 
 
-def step(u, data, w, coeff, dt_dz, decide_f32=False):
+def step(u, data, w, coeff, dt_dz, decide_f32=False, kappa=None, damping=False):
     """Returns (next padded state, mx, my)."""
     ni, nj, nk = _dims_padded(u)
     u = _f64(u, (nk, nj + 4, ni + 4))
     data = _f64(data, (nk, nj, ni))
     w = _f64(w, (nk + 1, nj, ni))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     nxt = np.empty_like(u)
     mx = np.zeros((nk, nj, ni + 1), np.uint8)
     my = np.zeros((nk, nj + 1, ni), np.uint8)
-    lib().oracle_step(ni, nj, nk, _d(u), _d(data), _d(w), float(coeff), float(dt_dz),
-                      int(decide_f32), _d(nxt), _b(mx), _b(my))
+    lib().oracle_step_gen(ni, nj, nk, _d(u), _d(data), _d(w), float(coeff), kp, int(damping),
+                          float(dt_dz), int(decide_f32), _d(nxt), _b(mx), _b(my))
     return nxt, mx, my
 
 
-def hdiff_adjoint(lam, mx, my, coeff):
+def hdiff_adjoint(lam, mx, my, coeff, kappa=None, damping=False):
     nk, nj, ni = np.shape(lam)
     lam = _f64(lam, (nk, nj, ni))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     ubar = np.zeros((nk, nj + 4, ni + 4))
-    lib().oracle_hdiff_adjoint(ni, nj, nk, _d(lam), _b(mx), _b(my), float(coeff), _d(ubar))
+    lib().oracle_hdiff_adjoint_gen(ni, nj, nk, _d(lam), _b(mx), _b(my), float(coeff), kp, int(damping),
+                                   _d(ubar))
     return ubar
 
 
@@ -171,39 +197,43 @@ def vadv_adjoint(xbar, w, dt_dz):
     return lam
 
 
-def step_adjoint(xbar, w, mx, my, coeff, dt_dz):
+def step_adjoint(xbar, w, mx, my, coeff, dt_dz, kappa=None, damping=False):
     """Returns (ubar padded, databar interior)."""
     nk, nj, ni = np.shape(xbar)
     xbar = _f64(xbar, (nk, nj, ni))
     w = _f64(w, (nk + 1, nj, ni))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     ubar = np.zeros((nk, nj + 4, ni + 4))
     dbar = np.zeros((nk, nj, ni))
-    lib().oracle_step_adjoint(ni, nj, nk, _d(xbar), _d(w), _b(mx), _b(my), float(coeff),
-                              float(dt_dz), _d(ubar), _d(dbar))
+    lib().oracle_step_adjoint_gen(ni, nj, nk, _d(xbar), _d(w), _b(mx), _b(my), float(coeff), kp,
+                                  int(damping), float(dt_dz), _d(ubar), _d(dbar))
     return ubar, dbar
 
 
-def step_tangent(v, w, mx, my, coeff, dt_dz):
+def step_tangent(v, w, mx, my, coeff, dt_dz, kappa=None, damping=False):
     ni, nj, nk = _dims_padded(v)
     v = _f64(v, (nk, nj + 4, ni + 4))
     w = _f64(w, (nk + 1, nj, ni))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     dx = np.zeros((nk, nj, ni))
-    lib().oracle_step_tangent(ni, nj, nk, _d(v), _d(w), _b(mx), _b(my), float(coeff),
-                              float(dt_dz), _d(dx))
+    lib().oracle_step_tangent_gen(ni, nj, nk, _d(v), _d(w), _b(mx), _b(my), float(coeff), kp,
+                                  int(damping), float(dt_dz), _d(dx))
     return dx
 
 
-def hdiff_tangent(v, mx, my, coeff):
+def hdiff_tangent(v, mx, my, coeff, kappa=None, damping=False):
     ni, nj, nk = _dims_padded(v)
     v = _f64(v, (nk, nj + 4, ni + 4))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
+    keep, kp = _kappa(kappa, nk, nj, ni)
     dh = np.zeros((nk, nj, ni))
-    lib().oracle_hdiff_tangent(ni, nj, nk, _d(v), _b(mx), _b(my), float(coeff), _d(dh))
+    lib().oracle_hdiff_tangent_gen(ni, nj, nk, _d(v), _b(mx), _b(my), float(coeff), kp, int(damping),
+                                   _d(dh))
     return dh
 
 
@@ -225,25 +255,37 @@ def laplacian(u):
     return lap
 
 
-def hdiff_divergence(u, mx, my):
+def hdiff_divergence(u, mx, my, damping=False):
     """D(u): the divergence of the limited fluxes on the interior."""
     ni, nj, nk = _dims_padded(u)
     u = _f64(u, (nk, nj + 4, ni + 4))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
     div = np.zeros((nk, nj, ni))
-    lib().oracle_hdiff_divergence(ni, nj, nk, _d(u), _b(mx), _b(my), _d(div))
+    lib().oracle_hdiff_divergence_form(ni, nj, nk, _d(u), _b(mx), _b(my), int(damping), _d(div))
     return div
 
 
-def coeff_grad(u, lam, mx, my):
+def coeff_grad(u, lam, mx, my, damping=False):
     """dL/dcoeff = -sum lam * D(u) (compensated sum)."""
     ni, nj, nk = _dims_padded(u)
     u = _f64(u, (nk, nj + 4, ni + 4))
     lam = _f64(lam, (nk, nj, ni))
     mx = _u8(mx, (nk, nj, ni + 1))
     my = _u8(my, (nk, nj + 1, ni))
-    return float(lib().oracle_coeff_grad(ni, nj, nk, _d(u), _d(lam), _b(mx), _b(my)))
+    return float(lib().oracle_coeff_grad_form(ni, nj, nk, _d(u), _d(lam), _b(mx), _b(my), int(damping)))
+
+
+def coeff_field_grad(u, lam, mx, my, damping=False):
+    """dL/dkappa(p) = -lam(p) D(u)(p) for a per-point coefficient field."""
+    ni, nj, nk = _dims_padded(u)
+    u = _f64(u, (nk, nj + 4, ni + 4))
+    lam = _f64(lam, (nk, nj, ni))
+    mx = _u8(mx, (nk, nj, ni + 1))
+    my = _u8(my, (nk, nj + 1, ni))
+    kbar = np.zeros((nk, nj, ni))
+    lib().oracle_coeff_field_grad(ni, nj, nk, _d(u), _d(lam), _b(mx), _b(my), int(damping), _d(kbar))
+    return kbar
 
 
 def w_grad(w, x, lam, dt_dz):

@@ -15,6 +15,8 @@ two benchmark stencils of Sec. 3.1 at the sizes below):
   ``w ~ U[-1,1]`` on nk+1 staggered levels; ``data ~ U[-0.1,0.1]``;
 * binary32 runs use ``astype(float32)`` of the same draws;
 * scalars: coeff = 0.025, dt/dz = 0.5;
+* a per-point coefficient field (the generalised diffusion) is drawn
+  ``U[coeff/2, 3 coeff/2)`` on the interior from child 103;
 * the batched workload draws 32 (ni, nj, nk) triples, integers uniform and
   inclusive in [48,384] x [48,384] x [40,137], then one child per field.
 
@@ -53,6 +55,7 @@ BATCH_RANGE = ((48, 384), (48, 384), (40, 137))
 COTANGENT_CHILD = 100
 DOT_CHILD = 101
 FD_CHILD = 102
+COEFF_FIELD_CHILD = 103
 
 
 def _children(n: int):
@@ -102,6 +105,11 @@ def dot_vectors(ni: int, nj: int, nk: int):
     v = r.uniform(-1.0, 1.0, (nk, nj + 2 * HALO, ni + 2 * HALO))
     wv = r.uniform(-1.0, 1.0, (nk, nj, ni))
     return v, wv
+
+
+def coeff_field(ni: int, nj: int, nk: int, child: int = COEFF_FIELD_CHILD) -> np.ndarray:
+    """Per-point diffusion coefficient on the interior, U[coeff/2, 3 coeff/2)."""
+    return rng_for(child).uniform(0.5 * COEFF, 1.5 * COEFF, (nk, nj, ni))
 
 
 def fd_points(ni: int, nj: int, nk: int, count: int = 64) -> np.ndarray:
