@@ -45,23 +45,43 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 #endif
 
 // ------------------------------------------------------------------ queue
+// The work list is written by the upload kernels before the launch and is
+// the same for every lane: values read from it are taken from lane 0, so
+// the field, its argument block and the buffer descriptors built from it
+// are known to be uniform and stay in SGPRs.
+__device__ __forceinline__ int uniform_ld(const int32_t* p) { return __builtin_amdgcn_readfirstlane(*p); }
+
+template <typename S>
+__device__ __forceinline__ S uniform_ld(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "argument blocks are whole words");
+  struct Words {
+    uint32_t w[sizeof(S) / 4];
+  } v;
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) v.w[i] = __builtin_amdgcn_readfirstlane(q[i]);
+  return __builtin_bit_cast(S, v);
+}
+
 // Next work item of the workgroup (uniform), or -1 when the queue is empty.
 // The table upload of each call zeroes the counter, so no reset is needed.
 __device__ __forceinline__ int next_work(BatchHeader* h, int* slot) {
   if (threadIdx.x == 0) *slot = (int)atomicAdd(&h->queue, 1u);
   __syncthreads();
-  const int w = *slot;
+  // every lane reads the same value; taking lane 0's makes it a scalar, so
+  // the item's argument block and buffer descriptors stay in SGPRs
+  const int w = __builtin_amdgcn_readfirstlane(*slot);
   __syncthreads();  // every lane has the value before the slot is reused
-  return w < h->total ? w : -1;
+  return w < uniform_ld(&h->total) ? w : -1;
 }
 
 // Field of work item w: the last e with prefix[e] <= w.
 __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
   const int32_t* p = h->prefix();
-  int lo = 0, hi = h->n - 1;
+  int lo = 0, hi = uniform_ld(&h->n) - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (p[mid] <= w) lo = mid;
+    if (uniform_ld(p + mid) <= w) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -78,8 +98,8 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     const int w = next_work(h, &slot);
     if (w < 0) break;
     const int e = find_entry(h, w);
-    const StepArgs<T> A = ent[e];
-    const int tile = w - h->prefix()[e];
+    const StepArgs<T> A = uniform_ld(ent + e);
+    const int tile = w - uniform_ld(h->prefix() + e);
     if constexpr (sizeof(T) == 8) {
       if (A.nk <= 80)
         step_split_tile<T, TI, TJ, 40, GT4MI_PD, MASK, 1>(A, tile, sm);
@@ -101,8 +121,8 @@ __global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const 
     const int w = next_work(h, &slot);
     if (w < 0) break;
     const int e = find_entry(h, w);
-    const StepArgs<T> A = ent[e];
-    const int tile = w - h->prefix()[e];
+    const StepArgs<T> A = uniform_ld(ent + e);
+    const int tile = w - uniform_ld(h->prefix() + e);
     if constexpr (sizeof(T) == 8) {
       if (A.nk <= 96)
         column_split_tile<T, 48, GT4MI_COL_PD, true, 1>(A, tile, xch);
@@ -124,10 +144,10 @@ __global__ void __launch_bounds__(TI* TJ) k_hadj_batched(BatchHeader* h, const A
     const int w = next_work(h, &slot);
     if (w < 0) break;
     const int e = find_entry(h, w);
-    const AdjArgs<T> A = ent[e];
-    const int local = w - h->prefix()[e];
+    const AdjArgs<T> A = uniform_ld(ent + e);
+    const int local = w - uniform_ld(h->prefix() + e);
     const int tile = local % A.ntiles, kb = local / A.ntiles;
-    const int kper = h->kper()[e];
+    const int kper = uniform_ld(h->kper() + e);
     hdiff_adjoint_tile<T, TI, TJ>(A, tile, kb * kper, min(kb * kper + kper, A.nk), sm);
     __syncthreads();
   }
