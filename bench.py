@@ -249,7 +249,7 @@ def main():
     gbs = b64 / t_step / 1e9
     ti, tj, col = tuned["f64"]
     nkh = nk - nk // 2
-    kname = (f"k_step_split<double, {ti}, {tj}, {split_class(nkh)}, 2, false, {1 if nk <= 80 else 2}>"
+    kname = (f"k_step_split<double, {ti}, {tj}, {split_class(nkh)}, 2, false, {1 if nk <= 80 else 2}, false>"
              if col == api.COLUMN_SPLIT else f"k_step_fused<double, {ti}, {tj}, 80, 2, {col}>")
     # measured HBM bytes of this kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE,
     # copy-calibrated), valid only while the kernel sources are unchanged

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define STENCIL_ABI_VERSION 1
+#define STENCIL_ABI_VERSION 2
 #define STENCIL_HALO 2
 
 typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype;
@@ -113,6 +113,18 @@ typedef enum {
 } stencil_boundary;
 
 /* Optional per-call options; pass NULL for defaults. */
+/* Form of the horizontal diffusion's Laplacian stage (Sec. 3.1 names the
+ * stencil; its benchmark definition is the STATED form).  The DAMPING form
+ * takes the discrete Laplacian itself, so that with every flux kept the
+ * update is u - coeff * (discrete Laplacian applied twice), fourth-order
+ * damping, where the stated form adds that term.  The limiter rule and the
+ * update formula are the same in both; the limiter then keeps only fluxes
+ * that run down the gradient of u. */
+typedef enum {
+  STENCIL_HDIFF_STATED = 0, /* lap = 4u - (u[i-1] + u[i+1] + u[j-1] + u[j+1]) */
+  STENCIL_HDIFF_DAMPING = 1 /* lap = (u[i-1] + u[i+1] + u[j-1] + u[j+1]) - 4u */
+} stencil_hdiff_form;
+
 typedef struct {
   int32_t impl;         /* stencil_impl */
   int32_t tile_i;       /* horizontal tile of the fused kernels; 0 = tuned */
@@ -123,6 +135,19 @@ typedef struct {
   int32_t boundary;     /* stencil_boundary of stencil_step (and of the graph
                            loop, which calls it): PERIODIC needs an output
                            with the 2-point halo */
+  /* The generalised horizontal diffusion (stencil_hdiff, stencil_step, the
+   * graph loop and their adjoints; fused kernels only, the step with
+   * nk <= 144 in FP64 / 160 in FP32; PLAIN, the batched calls and longer
+   * columns return STENCIL_E_UNSUPPORTED).  Zero-initialised options keep
+   * the stated form with the scalar coefficient. */
+  int32_t hdiff_form;               /* stencil_hdiff_form */
+  const stencil_field* coeff_field; /* NULL: the scalar coeff argument.  Else a
+                                       per-point coefficient kappa(i,j,k) on the
+                                       domain (interior layout, like data) that
+                                       replaces it in the update, out = u -
+                                       kappa * div; the scalar is then ignored
+                                       (the adjoints take their coefficient
+                                       from here too).  Read, never written. */
 } stencil_options;
 
 typedef enum {
@@ -162,7 +187,8 @@ size_t stencil_workspace_bytes(int op, stencil_dtype dtype, const int64_t domain
 /* Horizontal diffusion (Sec. 3.1).  u: read on the domain plus a 2-point
  * halo in i and j.  out: the interior is written, its halo is untouched.
  * mask: NULL, or stencil_mask_bytes(domain) device bytes that receive the
- * limiter decisions. */
+ * limiter decisions.  opts->hdiff_form and opts->coeff_field select the
+ * generalised diffusion (the coefficient field may not overlap out). */
 int stencil_hdiff(stencil_dtype dtype, const stencil_field* u, stencil_field* out,
                   const int64_t domain[3], double coeff, void* mask,
                   const stencil_options* opts, hipStream_t stream);
@@ -177,7 +203,8 @@ int stencil_vadv(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
 /* One time step: out = vadv(hdiff(u), data, w).  Arguments as above; the
  * halo of out is untouched (ping-pong buffers with equal halos keep a
  * frozen boundary) unless opts->boundary is PERIODIC, which then fills it
- * from the new interior. */
+ * from the new interior.  The diffusion follows opts->hdiff_form and
+ * opts->coeff_field as in stencil_hdiff. */
 int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_field* data,
                  const stencil_field* w, stencil_field* out, const int64_t domain[3],
                  double coeff, double dt_dz, void* mask, const stencil_options* opts,
@@ -187,7 +214,9 @@ int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
 /* u_bar = J_hdiff^T out_bar with the forward limiter mask held fixed.
  * out_bar: domain.  u_bar: written over the domain plus its 2-point halo
  * (every padded point is overwritten, the corner points never read by the
- * forward stencil receive 0).  mask: from a forward call on this domain. */
+ * forward stencil receive 0).  mask: from a forward call on this domain
+ * with the same opts->hdiff_form; opts->coeff_field, when set, is the
+ * forward's per-point coefficient. */
 int stencil_hdiff_adjoint(stencil_dtype dtype, const stencil_field* out_bar, const void* mask,
                           stencil_field* u_bar, const int64_t domain[3], double coeff,
                           const stencil_options* opts, hipStream_t stream);
@@ -200,7 +229,8 @@ int stencil_vadv_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
 
 /* Adjoint of stencil_step: lambda = T^{-T} x_bar; u_bar = J_hdiff^T lambda
  * (domain plus halo); data_bar = lambda if data_bar is not NULL (else the
- * workspace of opts holds lambda, stencil_workspace_bytes(STEP_ADJOINT)). */
+ * workspace of opts holds lambda, stencil_workspace_bytes(STEP_ADJOINT)).
+ * opts->hdiff_form and opts->coeff_field as for stencil_hdiff_adjoint. */
 int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar,
                          const stencil_field* w, const void* mask, stencil_field* u_bar,
                          stencil_field* data_bar, const int64_t domain[3], double coeff,
@@ -232,12 +262,29 @@ int stencil_halo_update(stencil_dtype dtype, stencil_field* f, const int64_t dom
  * Either output may be NULL (not both).  coeff_bar needs a device
  * workspace of stencil_param_workspace_bytes(domain) bytes (8-byte aligned)
  * for the per-tile sums.  Outputs may not overlap inputs, the workspace or
- * each other (STENCIL_E_ALIAS). */
+ * each other (STENCIL_E_ALIAS).  opts (NULL: defaults): hdiff_form selects
+ * the D of coeff_bar; a forward with opts->coeff_field has no scalar
+ * coefficient, so coeff_bar must then be NULL (STENCIL_E_ARG; its gradient
+ * is stencil_coeff_field_adjoint's). */
 size_t stencil_param_workspace_bytes(stencil_dtype dtype, const int64_t domain[3]);
 int stencil_step_param_adjoint(stencil_dtype dtype, const stencil_field* u, const stencil_field* w,
                                const stencil_field* x, const stencil_field* lam,
                                stencil_field* w_bar, double* coeff_bar, const int64_t domain[3],
-                               double dt_dz, void* ws, size_t ws_bytes, hipStream_t stream);
+                               double dt_dz, const stencil_options* opts, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/* Gradient with respect to the per-point coefficient of the generalised
+ * diffusion: out(p) depends on kappa(p) only through -kappa(p) D(u)(p), so
+ *   kappa_bar(p) = -lam(p) D(u)(p)
+ * with D for opts->hdiff_form (NULL opts: the stated form) and lam the
+ * cotangent of the diffusion's output: out_bar for stencil_hdiff, the
+ * data_bar of stencil_step_adjoint for a step.  u: the forward input
+ * (domain plus 2-point halo); lam, kappa_bar: domain.  kappa_bar may not
+ * overlap u or lam (STENCIL_E_ALIAS).  The limiter decisions are recomputed
+ * from u, as the forward took them. */
+int stencil_coeff_field_adjoint(stencil_dtype dtype, const stencil_field* u, const stencil_field* lam,
+                                stencil_field* kappa_bar, const int64_t domain[3],
+                                const stencil_options* opts, hipStream_t stream);
 
 /* ------------------------------------------------------------- batched */
 /* Many independent fields of uneven sizes in one persistent launch (each

@@ -33,6 +33,7 @@ CODES = {v: k for k, v in ERRORS.items()}
 IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN = 0, 1, 2
 COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF, COLUMN_SPLIT = 0, 1, 2, 3
 BOUNDARY_FROZEN, BOUNDARY_PERIODIC = 0, 1
+HDIFF_STATED, HDIFF_DAMPING = 0, 1
 OP_HDIFF, OP_VADV, OP_STEP, OP_HDIFF_ADJOINT, OP_VADV_ADJOINT, OP_STEP_ADJOINT = range(6)
 
 I64x3 = ctypes.c_int64 * 3
@@ -51,6 +52,8 @@ class StencilOptions(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("boundary", ctypes.c_int32),
+        ("hdiff_form", ctypes.c_int32),
+        ("coeff_field", ctypes.POINTER(StencilField)),
     ]
 
 
@@ -87,6 +90,9 @@ class StencilError(RuntimeError):
         self.name = ERRORS.get(code, str(code))
 
 
+# the ABI this binding marshals for (stencil_version() of the library)
+ABI_VERSION = 2
+
 _lock = threading.Lock()
 _lib = None
 
@@ -113,7 +119,8 @@ SIGNATURES = {
     "stencil_step_adjoint": (I, [I, PF, PF, VP, PF, PF, PI64, D, D, PO, VP]),
     "stencil_param_workspace_bytes": (SZ, [I, PI64]),
     "stencil_halo_update": (I, [I, PF, PI64, I, VP]),
-    "stencil_step_param_adjoint": (I, [I, PF, PF, PF, PF, PF, VP, PI64, D, VP, SZ, VP]),
+    "stencil_step_param_adjoint": (I, [I, PF, PF, PF, PF, PF, VP, PI64, D, PO, VP, SZ, VP]),
+    "stencil_coeff_field_adjoint": (I, [I, PF, PF, PF, PI64, PO, VP]),
     "stencil_batch_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchItem)]),
     "stencil_batch_adjoint_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchAdjointItem)]),
     "stencil_step_batched": (I, [I, I, ctypes.POINTER(StencilBatchItem), VP, SZ, PO, VP]),
@@ -144,6 +151,9 @@ def lib():
                     fn = getattr(L, name)
                     fn.restype = res
                     fn.argtypes = args
+                if L.stencil_version() != ABI_VERSION:
+                    raise RuntimeError(f"{LIB_PATH} has ABI {L.stencil_version()}, this binding needs "
+                                       f"{ABI_VERSION}: rebuild the library")
                 _lib = L
     return _lib
 

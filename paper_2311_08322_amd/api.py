@@ -16,18 +16,19 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (BOUNDARY_FROZEN, BOUNDARY_PERIODIC, COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
+from ._lib import (BOUNDARY_FROZEN, BOUNDARY_PERIODIC, HDIFF_DAMPING, HDIFF_STATED, COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
                    IMPL_PLAIN, OP_HDIFF, OP_HDIFF_ADJOINT, OP_STEP, OP_STEP_ADJOINT, OP_VADV,
                    OP_VADV_ADJOINT, StencilError)
 
 __all__ = [
     "Field", "Options", "StencilError", "F32", "F64",
-    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "BOUNDARY_FROZEN", "BOUNDARY_PERIODIC", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
+    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "BOUNDARY_FROZEN", "BOUNDARY_PERIODIC", "HDIFF_STATED", "HDIFF_DAMPING", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
     "OP_HDIFF", "OP_VADV", "OP_STEP", "OP_HDIFF_ADJOINT", "OP_VADV_ADJOINT", "OP_STEP_ADJOINT",
     "stencil_version", "stencil_last_error", "stencil_max_fused_nk", "stencil_mask_bytes",
     "stencil_workspace_bytes", "stencil_hdiff", "stencil_vadv", "stencil_step",
     "stencil_hdiff_adjoint", "stencil_vadv_adjoint", "stencil_step_adjoint",
-    "stencil_param_workspace_bytes", "stencil_step_param_adjoint", "stencil_halo_update",
+    "stencil_param_workspace_bytes", "stencil_step_param_adjoint", "stencil_coeff_field_adjoint",
+    "stencil_halo_update",
     "stencil_batch_workspace_bytes", "stencil_batch_adjoint_workspace_bytes",
     "stencil_step_batched", "stencil_step_adjoint_batched", "stencil_graph_capture_steps",
     "stencil_graph_launch", "stencil_graph_destroy", "stencil_autotune", "stencil_tuning_lookup",
@@ -64,6 +65,8 @@ class Options:
     column_store: int = COLUMN_AUTO
     workspace: Optional[torch.Tensor] = None
     boundary: int = BOUNDARY_FROZEN
+    hdiff_form: int = HDIFF_STATED
+    coeff_field: Optional["Field"] = None  # per-point coefficient (interior layout)
 
     def c(self) -> _lib.StencilOptions:
         o = _lib.StencilOptions()
@@ -75,6 +78,11 @@ class Options:
             o.workspace = self.workspace.data_ptr()
             o.workspace_bytes = self.workspace.numel() * self.workspace.element_size()
         o.boundary = self.boundary
+        o.hdiff_form = self.hdiff_form
+        if self.coeff_field is not None:
+            cf = self.coeff_field if isinstance(self.coeff_field, _lib.StencilField) else self.coeff_field.c()
+            o._coeff_field = cf  # keep the descriptor alive with the options
+            o.coeff_field = ctypes.pointer(cf)
         return o
 
 
@@ -196,13 +204,20 @@ def stencil_param_workspace_bytes(dtype, domain) -> int:
 
 
 def stencil_step_param_adjoint(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, ws=None, stream=None,
-                               dtype=None):
+                               dtype=None, opts=None):
     """coeff_bar: a device tensor holding one float64 (or None); w_bar: a
     staggered field (or None); ws: the workspace tensor for coeff_bar."""
     nb = 0 if ws is None else ws.numel() * ws.element_size()
     _lib.check(_lib.lib().stencil_step_param_adjoint(
         _dt(dtype, lam), _fld(u), _fld(w), _fld(x), _fld(lam), _fld(w_bar), _ptr(coeff_bar),
-        _lib.domain3(domain), float(dt_dz), _ptr(ws), nb, _stream(stream)))
+        _lib.domain3(domain), float(dt_dz), _opts(opts), _ptr(ws), nb, _stream(stream)))
+
+
+def stencil_coeff_field_adjoint(u, lam, kappa_bar, domain, opts=None, stream=None, dtype=None):
+    """kappa_bar(p) = -lam(p) D(u)(p): the gradient of a per-point coefficient."""
+    _lib.check(_lib.lib().stencil_coeff_field_adjoint(
+        _dt(dtype, lam, kappa_bar), _fld(u), _fld(lam), _fld(kappa_bar), _lib.domain3(domain), _opts(opts),
+        _stream(stream)))
 
 
 # ------------------------------------------------------------------ batched

@@ -42,6 +42,8 @@ def _units():
         for ti in (64, 32, 16):
             u.append(("k_step_inst.hip", f"split_{t}_{ti}",
                       [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", *UNROLL]))
+            u.append(("k_step_inst.hip", f"splitvar_{t}_{ti}",
+                      [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", "-DGT4MI_VAR", *UNROLL]))
         for col in cols:
             u.append(("k_step_inst.hip", f"vadv_{t}_c{col}",
                       [f"-DGT4MI_T={t}", "-DGT4MI_VADV", f"-DGT4MI_COL={col}", *UNROLL]))

@@ -152,6 +152,8 @@ ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, co
   }
   r.ws = o ? o->workspace : nullptr;
   r.ws_bytes = o ? o->workspace_bytes : 0;
+  r.form = o ? o->hdiff_form : STENCIL_HDIFF_STATED;
+  r.kappa = o ? o->coeff_field : nullptr;
   return r;
 }
 
@@ -169,7 +171,43 @@ int check_opts(const stencil_options* o) {
   if (o->workspace_bytes && !o->workspace) return fail(STENCIL_E_NULL, "options.workspace is NULL");
   if (o->boundary != STENCIL_BOUNDARY_FROZEN && o->boundary != STENCIL_BOUNDARY_PERIODIC)
     return fail(STENCIL_E_ARG, "options.boundary = %d unknown", (int)o->boundary);
+  if (o->hdiff_form != STENCIL_HDIFF_STATED && o->hdiff_form != STENCIL_HDIFF_DAMPING)
+    return fail(STENCIL_E_ARG, "options.hdiff_form = %d unknown", (int)o->hdiff_form);
   return STENCIL_OK;
+}
+
+int check_coeff_field(const stencil_options* o, const int64_t* dom, size_t es, const char* oname, Span out) {
+  if (!o || !o->coeff_field) return STENCIL_OK;
+  TRY(check_field("coeff_field", o->coeff_field, dom, ROLE_INTERIOR, es));
+  return check_no_alias(oname, out, "coeff_field", span_of(o->coeff_field, es));
+}
+
+// The generalised diffusion in the forward argument block.
+template <typename T>
+static void apply_variant(StepArgs<T>& A, const ResolvedOpts& r) {
+  A.form = r.form;
+  if (r.kappa) {
+    A.kappa = at_origin<T>(r.kappa);
+    A.c_sj = r.kappa->stride[1];
+    A.c_sk = r.kappa->stride[2];
+  }
+}
+
+// ... and in the adjoint's: a scalar coefficient takes the form's sign
+// (the damping form is the stated one with the coefficient negated, its
+// saved mask already holding the damping decisions); a coefficient field
+// leaves the sign in coeff.
+template <typename T>
+static void apply_variant(AdjArgs<T>& A, const ResolvedOpts& r, double coeff) {
+  const double sg = r.form == STENCIL_HDIFF_DAMPING ? -1.0 : 1.0;
+  if (r.kappa) {
+    A.kappa = at_origin<T>(r.kappa);
+    A.c_sj = r.kappa->stride[1];
+    A.c_sk = r.kappa->stride[2];
+    A.coeff = (T)sg;
+  } else {
+    A.coeff = (T)(sg * coeff);
+  }
 }
 
 // Plain-form workspace carve-up: lap, fx, fy, c', d' (each 256-B aligned).
@@ -265,6 +303,7 @@ int run_hdiff(const stencil_field* u, stencil_field* out, const int64_t* dom, do
   StepArgs<T> A = step_args<T>(u, nullptr, nullptr, out, dom, coeff, 0.0, mask);
   if (r.impl == STENCIL_IMPL_PLAIN)
     return hip_status(launch_hdiff_plain<T>(A, carve_plain<T>(r.ws, dom), s), "hdiff (plain)");
+  apply_variant(A, r);
   return hip_status(launch_hdiff_fused<T>(A, r.tile_i, s), "hdiff (fused)");
 }
 
@@ -292,6 +331,7 @@ int run_step(const stencil_field* u, const stencil_field* data, const stencil_fi
     return hip_status(launch_vadv_plain<T>(B, ws, s), "step (plain vadv)");
   }
   StepArgs<T> A = step_args<T>(u, data, w, out, dom, coeff, dt_dz, mask);
+  apply_variant(A, r);
   return hip_status(launch_step_fused<T>(A, r.tile_i, r.column_store, s), "step (fused)");
 }
 
@@ -301,6 +341,7 @@ int run_hdiff_adjoint(const T* lam, int64_t l_sj, int64_t l_sk, const void* mask
                       hipStream_t s) {
   AdjArgs<T> A = adj_args<T>(nullptr, nullptr, const_cast<T*>(lam), l_sj, l_sk, ubar, dom, coeff,
                              0.0, (dom[0] == 0 || dom[1] == 0) ? nullptr : mask);
+  apply_variant(A, r, coeff);
   return hip_status(launch_hdiff_adjoint<T>(A, r.tile_i, s), "hdiff adjoint");
 }
 
@@ -393,13 +434,17 @@ int stencil_hdiff(stencil_dtype dtype, const stencil_field* u, stencil_field* ou
   TRY(check_field("u", u, domain, ROLE_HALO, es));
   TRY(check_field("out", out, domain, ROLE_INTERIOR, es));
   TRY(check_no_alias("out", span_of(out, es), "u", span_of(u, es)));
+  TRY(check_coeff_field(opts, domain, es, "out", span_of(out, es)));
   if (mask) {
     Span m{reinterpret_cast<uintptr_t>(mask), reinterpret_cast<uintptr_t>(mask) + stencil_mask_bytes(domain)};
     TRY(check_no_alias("mask", m, "u", span_of(u, es)));
     TRY(check_no_alias("mask", m, "out", span_of(out, es)));
+    if (opts && opts->coeff_field) TRY(check_no_alias("mask", m, "coeff_field", span_of(opts->coeff_field, es)));
   }
   if (domain_empty(domain)) return ok();
   ResolvedOpts r = resolve_opts(opts, dtype, STENCIL_OP_HDIFF, domain);
+  if (variant_opts(opts) && r.impl == STENCIL_IMPL_PLAIN)
+    return fail(STENCIL_E_UNSUPPORTED, "the generalised diffusion runs the fused kernels only");
   if (r.impl == STENCIL_IMPL_PLAIN) TRY(need_plain_ws(r, plain_ws_bytes(es, domain)));
   TRY(check_device());
   return dtype == STENCIL_F64 ? run_hdiff<double>(u, out, domain, coeff, mask, r, stream)
@@ -453,9 +498,18 @@ int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
     TRY(check_no_alias("mask", m, "out", so));
     TRY(check_no_alias("mask", m, "data", span_of(data, es)));
     TRY(check_no_alias("mask", m, "w", span_of(w, es)));
+    if (opts && opts->coeff_field) TRY(check_no_alias("mask", m, "coeff_field", span_of(opts->coeff_field, es)));
   }
+  TRY(check_coeff_field(opts, domain, es, "out", so));
   if (domain_empty(domain)) return ok();
   ResolvedOpts r = resolve_opts(opts, dtype, STENCIL_OP_STEP, domain);
+  if (variant_opts(opts)) {
+    if (r.impl == STENCIL_IMPL_PLAIN)
+      return fail(STENCIL_E_UNSUPPORTED, "the generalised diffusion runs the fused kernels only");
+    if (domain[2] > split_step_limit((int)es))
+      return fail(STENCIL_E_UNSUPPORTED, "the generalised step takes nk <= %d (nk = %lld)",
+                  split_step_limit((int)es), (long long)domain[2]);
+  }
   TRY(fused_nk_ok(r, domain));
   if (r.impl == STENCIL_IMPL_PLAIN) TRY(need_plain_ws(r, plain_ws_bytes(es, domain)));
   TRY(check_device());
@@ -491,6 +545,7 @@ int stencil_hdiff_adjoint(stencil_dtype dtype, const stencil_field* out_bar, con
   TRY(check_field("u_bar", u_bar, domain, ROLE_HALO, es));
   const Span sb = span_of(u_bar, es);
   TRY(check_no_alias("u_bar", sb, "out_bar", span_of(out_bar, es)));
+  TRY(check_coeff_field(opts, domain, es, "u_bar", sb));
   if (domain[2] == 0) return ok();
   const bool empty = domain_empty(domain);
   if (!mask && !empty) return fail(STENCIL_E_NULL, "mask is NULL");
@@ -555,7 +610,9 @@ int stencil_step_adjoint(stencil_dtype dtype, const stencil_field* x_bar, const 
     TRY(check_no_alias("data_bar", sd, "x_bar", sx));
     TRY(check_no_alias("data_bar", sd, "w", sw));
     TRY(check_no_alias("data_bar", sd, "u_bar", sb));
+    TRY(check_coeff_field(opts, domain, es, "data_bar", sd));
   }
+  TRY(check_coeff_field(opts, domain, es, "u_bar", sb));
   if (domain[2] == 0) return ok();
   const bool empty = domain_empty(domain);
   if (!mask && !empty) return fail(STENCIL_E_NULL, "mask is NULL");

@@ -44,7 +44,15 @@ struct ResolvedOpts {
   int column_store;
   void* ws;
   size_t ws_bytes;
+  int form;                    // stencil_hdiff_form
+  const stencil_field* kappa;  // per-point coefficient or null
 };
+// options that ask for the generalised diffusion
+inline bool variant_opts(const stencil_options* o) {
+  return o && (o->hdiff_form != STENCIL_HDIFF_STATED || o->coeff_field != nullptr);
+}
+// validates opts->coeff_field on the domain (if set) and that `out` does not overlap it
+int check_coeff_field(const stencil_options* o, const int64_t* dom, size_t es, const char* oname, Span out);
 ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, const int64_t* dom);
 size_t plain_ws_bytes(size_t es, const int64_t* dom);
 

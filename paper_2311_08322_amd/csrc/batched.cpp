@@ -66,6 +66,8 @@ int check_batch_args(stencil_dtype dtype, int n, const void* items, const stenci
     return fail(STENCIL_E_UNSUPPORTED, "the batched launch runs the fused kernels only");
   if (opts && opts->boundary != STENCIL_BOUNDARY_FROZEN)
     return fail(STENCIL_E_UNSUPPORTED, "the batched launch leaves halos frozen (use stencil_halo_update)");
+  if (variant_opts(opts))
+    return fail(STENCIL_E_UNSUPPORTED, "the batched launch runs the stated diffusion with a scalar coefficient");
   return STENCIL_OK;
 }
 

@@ -166,7 +166,20 @@ struct StepArgs {
   int tiles_i, ntiles;
   int k0, k1;  // level range of this launch (hdiff kernels)
   T coeff, r4;  // r4 = dt_dz / 4
+  // generalised diffusion (read only by the kernels built for it)
+  const T* kappa;  // per-point coefficient at domain (0,0,0), or null (scalar coeff)
+  int64_t c_sj, c_sk;
+  int form;  // 0: lap = 4u - sum of the neighbours; 1: the damping form, lap = sum - 4u
 };
+
+// Sign that folds the damping form into the stated one: its Laplacian,
+// fluxes and divergence are the exact negatives of the stated ones, so it
+// equals the stated diffusion with the limiter's gradient and the
+// coefficient multiplied by -1 (products with -1 are exact).
+template <typename T>
+__host__ __device__ inline T form_sign(int form) {
+  return form ? T(-1) : T(1);
+}
 
 template <typename T>
 struct AdjArgs {
@@ -183,6 +196,10 @@ struct AdjArgs {
   int ni, nj, nk;
   int tiles_i, ntiles;
   T coeff, r4;
+  // per-point coefficient of the generalised diffusion (null: the scalar
+  // coeff); with it, coeff holds the form's sign
+  const T* kappa;
+  int64_t c_sj, c_sk;
 };
 
 }  // namespace gt4mi

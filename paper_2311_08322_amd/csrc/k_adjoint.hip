@@ -121,12 +121,20 @@ hipError_t launch_hdiff_adjoint(AdjArgs<T> A, int tile_i, hipStream_t s) {
   int kper = A.nk;
   while (kper > 4 && (int64_t)A.ntiles * ((A.nk + kper - 1) / kper) < 4096) kper = (kper + 1) / 2;
   dim3 grid(A.ntiles, (A.nk + kper - 1) / kper), block(kWG);
-  if (tile_i == 64)
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, 64, 4>), grid, block, 0, s, A, kper);
-  else if (tile_i == 32)
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, 32, 8>), grid, block, 0, s, A, kper);
-  else
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, 16, 16>), grid, block, 0, s, A, kper);
+  const bool var = A.kappa != nullptr && A.lam != nullptr;  // per-point coefficient
+#define GT4MI_HADJ_LAUNCH(TI, TJ)                                                        \
+  if (var)                                                                               \
+    hipLaunchKernelGGL((k_hdiff_adjoint<T, TI, TJ, true>), grid, block, 0, s, A, kper);  \
+  else                                                                                   \
+    hipLaunchKernelGGL((k_hdiff_adjoint<T, TI, TJ, false>), grid, block, 0, s, A, kper);
+  if (tile_i == 64) {
+    GT4MI_HADJ_LAUNCH(64, 4)
+  } else if (tile_i == 32) {
+    GT4MI_HADJ_LAUNCH(32, 8)
+  } else {
+    GT4MI_HADJ_LAUNCH(16, 16)
+  }
+#undef GT4MI_HADJ_LAUNCH
   return hipGetLastError();
 }
 

@@ -48,7 +48,11 @@ struct HadjSmem {
 };
 
 // One output tile `tile` of the padded domain over levels [kbeg, kend).
-template <typename T, int TI, int TJ>
+// VAR: a per-point coefficient kappa (A.kappa, never null then): the box
+// holds kappa * lambda, whose differences the flux cotangents take (times
+// -A.coeff, the form's sign), and lambda(p) of the identity term is loaded
+// on its own.
+template <typename T, int TI, int TJ, bool VAR = false>
 __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile, int kbeg, int kend,
                                                    HadjSmem<T, TI, TJ>& sm) {
   using H = HadjShape<T, TI, TJ>;
@@ -70,13 +74,18 @@ __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile
 
   // level-invariant lane offsets
   uint32_t loff[NLD];
+  [[maybe_unused]] uint32_t koff[VAR ? NLD : 1];
 #pragma unroll
   for (int q = 0; q < NLD; ++q) {
     const int e = min(tid + q * NT, HN - 1);
     const int hj = e / HI, hi = e - hj * HI;
     const int gi = pi0 - 2 + hi, gj = pj0 - 2 + hj;
     loff[q] = in_I(gi, gj) ? ((uint32_t)gi + (uint32_t)gj * (uint32_t)A.l_sj) * S : kOffNone;
+    if constexpr (VAR) koff[q] = in_I(gi, gj) ? ((uint32_t)gi + (uint32_t)gj * (uint32_t)A.c_sj) * S : kOffNone;
   }
+  // lambda at the lane's own output point (VAR)
+  [[maybe_unused]] const uint32_t coff =
+      in_I(pi, pj) ? ((uint32_t)pi + (uint32_t)pj * (uint32_t)A.l_sj) * S : kOffNone;
   const int64_t W = A.ml.words;
   uint32_t xw_off[NGX], xe_off[NGX], yw_off[NGY], ye_off[NGY];
   int xbit[NGX], ybit[NGY];
@@ -104,6 +113,7 @@ __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile
   const uint32_t uoff = outp ? ((uint32_t)(pi + 2) + (uint32_t)(pj + 2) * (uint32_t)A.b_sj) * S : kOffNone;
 
   const LevelView vl = level_view<T>(A.lam, A.l_sj, A.l_sk, 0, 0, nj);
+  [[maybe_unused]] const LevelView vk = level_view<T>(VAR ? A.kappa : A.lam, A.c_sj, A.c_sk, 0, 0, nj);
   const LevelView vb = level_view<T>(A.ubar, A.b_sj, A.b_sk, -2, -2, nj + 4);
   const char* mbase = reinterpret_cast<const char*>(A.mask);
   const int64_t plane_xy = (int64_t)nj * W * 8;
@@ -113,12 +123,19 @@ __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile
   };
 
   T pl[NLD];
+  [[maybe_unused]] T pk[VAR ? NLD : 1], plc = T(0);
   uint64_t pxw[NGX], pyw[NGY];
   uint32_t pxe[NGX], pye[NGY];
   auto issue = [&](int k) {
     const auto rl = vl.at(k);
 #pragma unroll
     for (int q = 0; q < NLD; ++q) pl[q] = buf_ld(rl, loff[q], T());
+    if constexpr (VAR) {
+      const auto rk = vk.at(k);
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) pk[q] = buf_ld(rk, koff[q], T());
+      plc = buf_ld(rl, coff, T());
+    }
     const auto rx = mrsrc(A.ml.x_off, k, plane_xy, win_xy);
     const auto ry = mrsrc(A.ml.y_off, k, plane_xy, win_xy);
 #pragma unroll
@@ -144,8 +161,15 @@ __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile
 
   for (int k = kbeg; k < kend; ++k) {
     T* sl = slam[k & 1];
+    [[maybe_unused]] T lc = T(0);
+    if constexpr (VAR) {
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) sl[tid + q * NT] = pl[q];
+      for (int q = 0; q < NLD; ++q) sl[tid + q * NT] = pk[q] * pl[q];
+      lc = plc;
+    } else {
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) sl[tid + q * NT] = pl[q];
+    }
     bool kx[NGX], ky[NGY];
 #pragma unroll
     for (int q = 0; q < NGX; ++q) kx[q] = ((pxw[q] >> xbit[q]) & 1) | pxe[q];
@@ -182,18 +206,18 @@ __device__ __forceinline__ void hdiff_adjoint_tile(const AdjArgs<T>& A, int tile
     __syncthreads();
     {
       const int c = (tj + 1) * LI + (ti + 1);
-      const T lp = sl[(tj + 2) * HI + (ti + 2)];  // 0 outside the interior
+      const T lp = VAR ? lc : sl[(tj + 2) * HI + (ti + 2)];  // 0 outside the interior
       const T v = lp + T(4) * slb[c] - slb[c + 1] - slb[c - 1] - slb[c + LI] - slb[c - LI];
       buf_st(vb.at(k), uoff, v);
     }
   }
 }
 
-template <typename T, int TI, int TJ>
+template <typename T, int TI, int TJ, bool VAR>
 __global__ void __launch_bounds__(TI* TJ) k_hdiff_adjoint(AdjArgs<T> A, int kper) {
   __shared__ HadjSmem<T, TI, TJ> sm;
   const int kbeg = blockIdx.y * kper;
-  hdiff_adjoint_tile<T, TI, TJ>(A, xcd_tile(blockIdx.x, gridDim.x), kbeg, min(kbeg + kper, A.nk), sm);
+  hdiff_adjoint_tile<T, TI, TJ, VAR>(A, xcd_tile(blockIdx.x, gridDim.x), kbeg, min(kbeg + kper, A.nk), sm);
 }
 
 

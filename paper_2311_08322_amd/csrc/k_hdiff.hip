@@ -14,12 +14,20 @@ hipError_t launch_hdiff_fused(StepArgs<T> A, int tile_i, hipStream_t s) {
   A.k0 = 0;
   A.k1 = kper;
   dim3 grid(A.ntiles, (A.nk + kper - 1) / kper), block(kWG);
-  if (tile_i == 64)
-    hipLaunchKernelGGL((k_hdiff_fused<T, 64, 4>), grid, block, 0, s, A);
-  else if (tile_i == 32)
-    hipLaunchKernelGGL((k_hdiff_fused<T, 32, 8>), grid, block, 0, s, A);
-  else
-    hipLaunchKernelGGL((k_hdiff_fused<T, 16, 16>), grid, block, 0, s, A);
+  const bool var = A.kappa != nullptr || A.form != 0;  // the generalised diffusion
+#define GT4MI_HDIFF_LAUNCH(TI, TJ)                                                  \
+  if (var)                                                                          \
+    hipLaunchKernelGGL((k_hdiff_fused<T, TI, TJ, true>), grid, block, 0, s, A);    \
+  else                                                                              \
+    hipLaunchKernelGGL((k_hdiff_fused<T, TI, TJ, false>), grid, block, 0, s, A);
+  if (tile_i == 64) {
+    GT4MI_HDIFF_LAUNCH(64, 4)
+  } else if (tile_i == 32) {
+    GT4MI_HDIFF_LAUNCH(32, 8)
+  } else {
+    GT4MI_HDIFF_LAUNCH(16, 16)
+  }
+#undef GT4MI_HDIFF_LAUNCH
   return hipGetLastError();
 }
 

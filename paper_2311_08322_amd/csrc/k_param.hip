@@ -18,19 +18,21 @@ namespace gt4mi {
 
 // D(u) at the diamond's centre: the flux stage of the diffusion (the same
 // limiter and association as the forward kernels), without the update.
+// gs is the form's sign (form_sign): the damping form's divergence is gs
+// times the stated one taken with the limiter's gradient times gs.
 template <typename T>
-__device__ __forceinline__ T divergence_of(const Diamond<T>& d) {
+__device__ __forceinline__ T divergence_of(const Diamond<T>& d, T gs) {
   const T L00 = T(4) * d.u00 - ((d.um1 + d.up1) + (d.vm1 + d.vp1));
   const T Lp0 = T(4) * d.up1 - ((d.u00 + d.up2) + (d.mp + d.pp));
   const T Lm0 = T(4) * d.um1 - ((d.um2 + d.u00) + (d.mm + d.pm));
   const T L0p = T(4) * d.vp1 - ((d.pm + d.pp) + (d.u00 + d.vp2));
   const T L0m = T(4) * d.vm1 - ((d.mm + d.mp) + (d.vm2 + d.u00));
   const T fxr = Lp0 - L00, fxl = L00 - Lm0, fyr = L0p - L00, fyl = L00 - L0m;
-  const T Fxr = flux_kept(fxr, d.up1 - d.u00) ? fxr : T(0);
-  const T Fxl = flux_kept(fxl, d.u00 - d.um1) ? fxl : T(0);
-  const T Fyr = flux_kept(fyr, d.vp1 - d.u00) ? fyr : T(0);
-  const T Fyl = flux_kept(fyl, d.u00 - d.vm1) ? fyl : T(0);
-  return (Fxr - Fxl) + (Fyr - Fyl);
+  const T Fxr = flux_kept(fxr, gs * (d.up1 - d.u00)) ? fxr : T(0);
+  const T Fxl = flux_kept(fxl, gs * (d.u00 - d.um1)) ? fxl : T(0);
+  const T Fyr = flux_kept(fyr, gs * (d.vp1 - d.u00)) ? fyr : T(0);
+  const T Fyl = flux_kept(fyl, gs * (d.u00 - d.vm1)) ? fyl : T(0);
+  return gs * ((Fxr - Fxl) + (Fyr - Fyl));
 }
 
 // One workgroup per TI x TJ tile of the interior marches the levels with
@@ -38,7 +40,9 @@ __device__ __forceinline__ T divergence_of(const Diamond<T>& d) {
 // level's loads in flight) and accumulates lam * D(u) in FP64; the tile's
 // sum goes to partial[tile] (fixed order: the result does not depend on
 // scheduling).  A.data holds lam.
-template <typename T, int TI, int TJ>
+// FIELD: the gradient of a per-point coefficient instead, -lam(p) D(u)(p)
+// stored point by point into A.out (partial unused).
+template <typename T, int TI, int TJ, bool FIELD>
 __global__ void __launch_bounds__(TI* TJ) k_coeff_partial(StepArgs<T> A, double* partial) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
@@ -52,6 +56,10 @@ __global__ void __launch_bounds__(TI* TJ) k_coeff_partial(StepArgs<T> A, double*
   const LevelView vu = level_view(A.u, A.u_sj, A.u_sk, -2, -2, A.nj + 4);
   const LevelView vl = level_view(A.data, A.d_sj, A.d_sk, 0, 0, A.nj);
   const uint32_t loff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.d_sj) * S;
+  [[maybe_unused]] const LevelView vo = level_view<T>(A.out, A.o_sj, A.o_sk, 0, 0, A.nj);
+  [[maybe_unused]] const uint32_t ooff =
+      t.active ? ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.o_sj) * S : kOffNone;
+  const T gs = form_sign<T>(A.form);
   LevelCursor cu_{vu.base, vu.level_bytes, vu.window};
   LevelCursor cl{vl.base, vl.level_bytes, vl.window};
   const int nk = A.nk;
@@ -75,9 +83,13 @@ __global__ void __launch_bounds__(TI* TJ) k_coeff_partial(StepArgs<T> A, double*
     const T lam = nl;
     issue(k + 1);
     __syncthreads();
-    const T div = divergence_of(load_diamond<T, HI>(U + cu));
-    acc += t.active ? (double)lam * (double)div : 0.0;
+    const T div = divergence_of(load_diamond<T, HI>(U + cu), gs);
+    if constexpr (FIELD)
+      buf_st(vo.at(k), ooff, -(lam * div));
+    else
+      acc += t.active ? (double)lam * (double)div : 0.0;
   }
+  if constexpr (FIELD) return;
   red[tid] = acc;
   __syncthreads();
 #pragma unroll
@@ -155,7 +167,8 @@ hipError_t launch_param_grads(const StepArgs<T>& Ain, const WGradArgs<T>* W, dou
   A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
   const bool some = A.ni > 0 && A.nj > 0;
   if (coeff_bar) {
-    if (some && A.nk > 0) hipLaunchKernelGGL((k_coeff_partial<T, 64, 4>), dim3(A.ntiles), dim3(kWG), 0, s, A, partial);
+    if (some && A.nk > 0)
+      hipLaunchKernelGGL((k_coeff_partial<T, 64, 4, false>), dim3(A.ntiles), dim3(kWG), 0, s, A, partial);
     const int n = (some && A.nk > 0) ? A.ntiles : 0;
     hipLaunchKernelGGL(k_coeff_final, dim3(1), dim3(kWG), 0, s, partial, n, coeff_bar);
   }
@@ -168,6 +181,18 @@ hipError_t launch_param_grads(const StepArgs<T>& Ain, const WGradArgs<T>* W, dou
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_coeff_field_grad(const StepArgs<T>& Ain, hipStream_t s) {
+  StepArgs<T> A = Ain;
+  A.tiles_i = (A.ni + 63) / 64;
+  A.ntiles = A.tiles_i * ((A.nj + 3) / 4);
+  if (A.ni > 0 && A.nj > 0 && A.nk > 0)
+    hipLaunchKernelGGL((k_coeff_partial<T, 64, 4, true>), dim3(A.ntiles), dim3(kWG), 0, s, A, nullptr);
+  return hipGetLastError();
+}
+
+template hipError_t launch_coeff_field_grad<float>(const StepArgs<float>&, hipStream_t);
+template hipError_t launch_coeff_field_grad<double>(const StepArgs<double>&, hipStream_t);
 template hipError_t launch_param_grads<float>(const StepArgs<float>&, const WGradArgs<float>*, double*, double*,
                                               hipStream_t);
 template hipError_t launch_param_grads<double>(const StepArgs<double>&, const WGradArgs<double>*, double*, double*,

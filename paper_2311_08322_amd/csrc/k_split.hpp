@@ -103,7 +103,9 @@ struct SplitSmem {
   T xch[2][2][kWG];                            // innermost (e, f) of each half and column
 };
 
-template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL>
+// VAR: the generalised diffusion (per-point coefficient when A.kappa is
+// set, the scalar otherwise; the form's sign on the limiter and coefficient).
+template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL, bool VAR = false>
 __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, SplitSmem<T, TI, TJ>& sm) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
@@ -134,17 +136,24 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
   LevelCursor cur_u{vu.base + (int64_t)k0 * vu.level_bytes, dir * vu.level_bytes, vu.window};
   LevelCursor cur_d{vd.base + (int64_t)k0 * vd.level_bytes, dir * vd.level_bytes, vd.window};
   LevelCursor cur_w{vw.base + (int64_t)(half ? k0 : 1) * vw.level_bytes, dir * vw.level_bytes, vw.window};
-  T pu[PD][NLD], pd[PD], pw[PD];
+  // the coefficient field (VAR): a null field reads through an empty window
+  const bool has_kappa = VAR && A.kappa != nullptr;
+  const LevelView vk = level_view(has_kappa ? A.kappa : A.data, A.c_sj, A.c_sk, 0, 0, has_kappa ? A.nj : 0);
+  const uint32_t koff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.c_sj) * S;
+  LevelCursor cur_k{vk.base + (int64_t)k0 * vk.level_bytes, dir * vk.level_bytes, vk.window};
+  T pu[PD][NLD], pd[PD], pw[PD], pk[VAR ? PD : 1];
   auto issue = [&](int slot, int s) {
     const auto ru = cur_u.rsrc();
 #pragma unroll
     for (int q = 0; q < NLD; ++q) pu[slot][q] = buf_ld<GT4MI_CP_HALO>(ru, t.hoff[q], T());
     pd[slot] = buf_ld<GT4MI_CP_ONCE>(cur_d.rsrc(), doff, T());
     pw[slot] = buf_ld<GT4MI_CP_ONCE>(cur_w.rsrc(), woff, T());  // the w level new at this step
+    if constexpr (VAR) pk[slot] = buf_ld<GT4MI_CP_ONCE>(cur_k.rsrc(), koff, T());
     const bool go = s + 1 < nlev;
     cur_u.advance(go);
     cur_d.advance(go);
     cur_w.advance(go);
+    if constexpr (VAR) cur_k.advance(go);
   };
 #pragma unroll
   for (int s = 0; s < PD; ++s) issue(s, s);
@@ -153,6 +162,7 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
   T fv[COL == 1 ? NKH : 1];
   T wp = T(0), e = T(0), f = T(0);
   const T coeff = A.coeff;
+  [[maybe_unused]] const T gs = form_sign<T>(A.form);
   const T sn = half ? A.r4 : -A.r4;  // near coefficient per unit w: top a = -r/4 w, bottom c = +r/4 w
   const int cu = (t.tj + 2) * HI + (t.ti + 2);
   T hq = T(0), dq = T(0), wq = T(0);  // the previous step's diffused value, data and new w
@@ -186,6 +196,8 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
 #pragma unroll
     for (int q = 0; q < NLD; ++q) U[ltid + q * NT] = pu[slot][q];
     const T dk = pd[slot], wn = pw[slot];
+    [[maybe_unused]] T kk = coeff;
+    if constexpr (VAR) kk = has_kappa ? pk[slot] : coeff;
     if (s + PD < NKH) issue(slot, s + PD);
     __syncthreads();
     const Diamond<T> dm = load_diamond<T, HI>(U + cu);
@@ -196,7 +208,10 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
       else buf_st(vo.at(min(max(k0 + dir * (s - 1), 0), nk - 1)), act ? ooff : kOffNone, f);
     }
     bool kxr, kxl, kyr, kyl;
-    hq = hdiff_of(dm, coeff, kxr, kxl, kyr, kyl);
+    if constexpr (VAR)
+      hq = hdiff_var_of(dm, kk, gs, kxr, kxl, kyr, kyl);
+    else
+      hq = hdiff_of(dm, coeff, kxr, kxl, kyr, kyl);
     dq = dk;
     wq = wn;
     if constexpr (MASK) mr.record<TI>(min(max(k0 + dir * s, 0), nk - 1), s < nlev, active, kxr, kyr, kxl, kyl);
@@ -234,10 +249,10 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
 }
 
 
-template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL>
+template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL, bool VAR>
 __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   __shared__ SplitSmem<T, TI, TJ> sm;
-  step_split_tile<T, TI, TJ, NKH, PD, MASK, COL>(A, xcd_tile(blockIdx.x, gridDim.x), sm);
+  step_split_tile<T, TI, TJ, NKH, PD, MASK, COL, VAR>(A, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
 // One instantiation per half-column register class.  With the early exit a
@@ -253,16 +268,16 @@ constexpr int split_max_nk() {
   return sizeof(T) == 8 ? 2 * kSplitStagedNkhF64 : 160;
 }
 
-template <typename T, int TI, int TJ>
+template <typename T, int TI, int TJ, bool VAR>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s) {
   const dim3 grid(A.ntiles), block(2 * TI * TJ);
   const int nkh = A.nk - A.nk / 2;
 #define GT4MI_SPLIT_LAUNCH(N, C)                                                                     \
   {                                                                                                  \
     if (A.mask)                                                                                      \
-      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, true, C>), grid, block, 0, s, A);    \
+      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, true, C, VAR>), grid, block, 0, s, A); \
     else                                                                                             \
-      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, false, C>), grid, block, 0, s, A);   \
+      hipLaunchKernelGGL((k_step_split<T, TI, TJ, N, GT4MI_PD, false, C, VAR>), grid, block, 0, s, A); \
     return hipGetLastError();                                                                        \
   }
 #define GT4MI_SPLIT_CASE(N)                                                                  \

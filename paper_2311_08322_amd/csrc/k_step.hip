@@ -16,10 +16,17 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
   const int tj = kWG / tile_i;
   A.tiles_i = (A.ni + tile_i - 1) / tile_i;
   A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
+  if (A.kappa != nullptr || A.form != 0) {
+    // the generalised diffusion is built for the two-ended step only
+    if (A.nk > split_step_limit(sizeof(T))) return hipErrorInvalidValue;
+    if (tile_i == 64) return launch_split_classes<T, 64, 4, true>(A, s);
+    if (tile_i == 32) return launch_split_classes<T, 32, 8, true>(A, s);
+    return launch_split_classes<T, 16, 16, true>(A, s);
+  }
   if (col == 3 && A.nk <= split_step_limit(sizeof(T))) {  // STENCIL_COLUMN_SPLIT
-    if (tile_i == 64) return launch_split_classes<T, 64, 4>(A, s);
-    if (tile_i == 32) return launch_split_classes<T, 32, 8>(A, s);
-    return launch_split_classes<T, 16, 16>(A, s);
+    if (tile_i == 64) return launch_split_classes<T, 64, 4, false>(A, s);
+    if (tile_i == 32) return launch_split_classes<T, 32, 8, false>(A, s);
+    return launch_split_classes<T, 16, 16, false>(A, s);
   }
   if constexpr (sizeof(T) == 4) {
     // binary32 columns up to the largest class fit their registers

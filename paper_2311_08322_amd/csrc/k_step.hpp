@@ -127,6 +127,29 @@ __device__ __forceinline__ T hdiff_of(const Diamond<T>& d, T coeff, bool& kxr, b
   return d.u00 - coeff * ((Fxr - Fxl) + (Fyr - Fyl));
 }
 
+// The generalised diffusion: a per-point coefficient kap, and the form's
+// sign gs (form_sign) on the limiter's gradient and on the coefficient.
+// gs = -1 gives the damping form exactly: its fluxes are the negatives of
+// the stated ones, kept where f * (-g) <= 0, and u - kap * (-div) =
+// u - (-kap) * div.
+template <typename T>
+__device__ __forceinline__ T hdiff_var_of(const Diamond<T>& d, T kap, T gs, bool& kxr, bool& kxl, bool& kyr,
+                                          bool& kyl) {
+  const T L00 = T(4) * d.u00 - ((d.um1 + d.up1) + (d.vm1 + d.vp1));
+  const T Lp0 = T(4) * d.up1 - ((d.u00 + d.up2) + (d.mp + d.pp));
+  const T Lm0 = T(4) * d.um1 - ((d.um2 + d.u00) + (d.mm + d.pm));
+  const T L0p = T(4) * d.vp1 - ((d.pm + d.pp) + (d.u00 + d.vp2));
+  const T L0m = T(4) * d.vm1 - ((d.mm + d.mp) + (d.vm2 + d.u00));
+  const T fxr = Lp0 - L00, fxl = L00 - Lm0, fyr = L0p - L00, fyl = L00 - L0m;
+  kxr = flux_kept(fxr, gs * (d.up1 - d.u00));
+  kxl = flux_kept(fxl, gs * (d.u00 - d.um1));
+  kyr = flux_kept(fyr, gs * (d.vp1 - d.u00));
+  kyl = flux_kept(fyl, gs * (d.u00 - d.vm1));
+  const T Fxr = kxr ? fxr : T(0), Fxl = kxl ? fxl : T(0);
+  const T Fyr = kyr ? fyr : T(0), Fyl = kyl ? fyl : T(0);
+  return d.u00 - (gs * kap) * ((Fxr - Fxl) + (Fyr - Fyl));
+}
+
 template <typename T, int HI>
 __device__ __forceinline__ T hdiff_diamond(const T* __restrict__ c, T coeff, bool& kxr, bool& kxl,
                                            bool& kyr, bool& kyl) {
@@ -325,7 +348,9 @@ __global__ void __launch_bounds__(kWG) k_vadv_fused(StepArgs<T> A) {
 // ------------------------------------------------------------------ hdiff
 // Tile marched over the levels [kbeg, kend) of its workgroup, the next
 // level's u-tile prefetched in registers while the current one is computed.
-template <typename T, int TI, int TJ>
+// VAR: the generalised diffusion (per-point coefficient kappa when given,
+// else the scalar, and the form's sign).
+template <typename T, int TI, int TJ, bool VAR>
 __global__ void __launch_bounds__(TI* TJ) k_hdiff_fused(StepArgs<T> A) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
@@ -341,24 +366,37 @@ __global__ void __launch_bounds__(TI* TJ) k_hdiff_fused(StepArgs<T> A) {
   MaskWriter mw;
   if (A.mask) mw = MaskWriter::make<T, TI>(A, t.i0, t.i, t.j, active);
   const int cu = (t.tj + 2) * HI + (t.ti + 2);
-  T pu[NLD];
+  // the coefficient field (VAR): a null field reads through an empty window
+  // and the scalar is used instead
+  const bool has_kappa = VAR && A.kappa != nullptr;
+  const LevelView vk = level_view(has_kappa ? A.kappa : A.u, A.c_sj, A.c_sk, 0, 0, has_kappa ? A.nj : 0);
+  const uint32_t koff = ((uint32_t)t.ic + (uint32_t)t.jc * (uint32_t)A.c_sj) * (uint32_t)sizeof(T);
+  const T gs = form_sign<T>(A.form);
+  T pu[NLD], pk = T(0);
   {
     const auto ru = vu.at(kbeg);
 #pragma unroll
     for (int q = 0; q < NLD; ++q) pu[q] = buf_ld(ru, t.hoff[q], T());
+    if constexpr (VAR) pk = buf_ld(vk.at(kbeg), koff, T());
   }
   for (int k = kbeg; k < kend; ++k) {
     T* U = su[k & 1];
 #pragma unroll
     for (int q = 0; q < NLD; ++q) U[tid + q * NT] = pu[q];
+    const T kk = pk;
     if (k + 1 < kend) {
       const auto ru = vu.at(k + 1);
 #pragma unroll
       for (int q = 0; q < NLD; ++q) pu[q] = buf_ld(ru, t.hoff[q], T());
+      if constexpr (VAR) pk = buf_ld(vk.at(k + 1), koff, T());
     }
     __syncthreads();
     bool kxr, kxl, kyr, kyl;
-    const T h = hdiff_diamond<T, HI>(U + cu, A.coeff, kxr, kxl, kyr, kyl);
+    T h;
+    if constexpr (VAR)
+      h = hdiff_var_of(load_diamond<T, HI>(U + cu), has_kappa ? kk : A.coeff, gs, kxr, kxl, kyr, kyl);
+    else
+      h = hdiff_diamond<T, HI>(U + cu, A.coeff, kxr, kxl, kyr, kyl);
     if (A.mask) mw.record<TI>(k, active, kxr, kyr, kxl, kyl);
     if (active) buf_st(vo.at(k), ooff, h);
   }

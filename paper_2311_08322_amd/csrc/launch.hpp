@@ -18,7 +18,8 @@ template <typename T, int TI, int TJ, int COL>
 hipError_t launch_step_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int COL>
 hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
-template <typename T, int TI, int TJ>
+// VAR: the generalised diffusion (per-point coefficient, damping form)
+template <typename T, int TI, int TJ, bool VAR>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
 // two-ended column solve: ADJ = false, out = T^{-1}(u + data);
 // ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 144 (FP64) / 160 (FP32)
@@ -102,6 +103,11 @@ inline size_t coeff_partial_count(int64_t ni, int64_t nj) {
 template <typename T>
 hipError_t launch_param_grads(const StepArgs<T>& A, const WGradArgs<T>* W, double* partial, double* coeff_bar,
                               hipStream_t s);
+
+// gradient of a per-point coefficient: A.out(p) = -A.data(p) D(u)(p)
+// (A.data holds lam; A.form selects the Laplacian form)
+template <typename T>
+hipError_t launch_coeff_field_grad(const StepArgs<T>& A, hipStream_t s);
 
 // periodic halo fill of a padded field (p at domain (0,0,0); k_halo.hip)
 template <typename T>

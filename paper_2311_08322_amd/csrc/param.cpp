@@ -24,8 +24,10 @@ Span bytes_span(const void* p, size_t n) {
 
 template <typename T>
 int run(const stencil_field* u, const stencil_field* w, const stencil_field* x, const stencil_field* lam,
-        stencil_field* w_bar, double* coeff_bar, const int64_t* dom, double dt_dz, void* ws, hipStream_t s) {
+        stencil_field* w_bar, double* coeff_bar, const int64_t* dom, double dt_dz, int form, void* ws,
+        hipStream_t s) {
   StepArgs<T> A = step_args<T>(u, lam, nullptr, nullptr, dom, 0.0, dt_dz, nullptr);
+  A.form = form;
   WGradArgs<T> W;
   memset(&W, 0, sizeof W);
   if (w_bar) {
@@ -61,11 +63,15 @@ size_t stencil_param_workspace_bytes(stencil_dtype dtype, const int64_t domain[3
 
 int stencil_step_param_adjoint(stencil_dtype dtype, const stencil_field* u, const stencil_field* w,
                                const stencil_field* x, const stencil_field* lam, stencil_field* w_bar,
-                               double* coeff_bar, const int64_t domain[3], double dt_dz, void* ws,
-                               size_t ws_bytes, hipStream_t stream) {
+                               double* coeff_bar, const int64_t domain[3], double dt_dz,
+                               const stencil_options* opts, void* ws, size_t ws_bytes, hipStream_t stream) {
   TRY(check_dtype(dtype));
   TRY(check_domain(domain));
+  TRY(check_opts(opts));
   if (!w_bar && !coeff_bar) return fail(STENCIL_E_NULL, "w_bar and coeff_bar are both NULL");
+  if (coeff_bar && opts && opts->coeff_field)
+    return fail(STENCIL_E_ARG, "a step with a coefficient field has no scalar coeff_bar (stencil_coeff_field_adjoint)");
+  const int form = opts ? opts->hdiff_form : STENCIL_HDIFF_STATED;
   const size_t es = esize(dtype);
   TRY(check_field("lam", lam, domain, ROLE_INTERIOR, es));
   std::vector<Span> in{span_of(lam, es)};
@@ -100,8 +106,33 @@ int stencil_step_param_adjoint(stencil_dtype dtype, const stencil_field* u, cons
   }
   TRY(check_device());
   return dtype == STENCIL_F64
-             ? run<double>(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, ws, stream)
-             : run<float>(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, ws, stream);
+             ? run<double>(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, form, ws, stream)
+             : run<float>(u, w, x, lam, w_bar, coeff_bar, domain, dt_dz, form, ws, stream);
+}
+
+int stencil_coeff_field_adjoint(stencil_dtype dtype, const stencil_field* u, const stencil_field* lam,
+                                stencil_field* kappa_bar, const int64_t domain[3],
+                                const stencil_options* opts, hipStream_t stream) {
+  TRY(check_dtype(dtype));
+  TRY(check_domain(domain));
+  TRY(check_opts(opts));
+  const size_t es = esize(dtype);
+  TRY(check_field("u", u, domain, ROLE_HALO, es));
+  TRY(check_field("lam", lam, domain, ROLE_INTERIOR, es));
+  TRY(check_field("kappa_bar", kappa_bar, domain, ROLE_INTERIOR, es));
+  const Span sk = span_of(kappa_bar, es);
+  TRY(check_no_alias("kappa_bar", sk, "u", span_of(u, es)));
+  TRY(check_no_alias("kappa_bar", sk, "lam", span_of(lam, es)));
+  if (domain_empty(domain)) return ok();
+  TRY(check_device());
+  const int form = opts ? opts->hdiff_form : STENCIL_HDIFF_STATED;
+  auto go = [&](auto tag) -> int {
+    using T = decltype(tag);
+    StepArgs<T> A = step_args<T>(u, lam, nullptr, kappa_bar, domain, 0.0, 0.0, nullptr);
+    A.form = form;
+    return hip_status(launch_coeff_field_grad<T>(A, stream), "coefficient field gradient");
+  };
+  return dtype == STENCIL_F64 ? go(double(0)) : go(float(0));
 }
 
 }  // extern "C"

@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_limits(L):
-    assert L.stencil_version() == 1
+    assert L.stencil_version() == 2
     assert L.stencil_max_fused_nk(1) >= 137
 
 
@@ -356,7 +356,7 @@ def test_param_adjoint_validation(L):
     need = L.stencil_param_workspace_bytes(1, d)
     assert need >= 8 * 1 * 3 and need % 256 == 0  # one double per 64 x 4 tile
     call = lambda wbar=b(wb), coeff_bar=cb, ws=ws, nb=need: L.stencil_step_param_adjoint(  # noqa: E731
-        1, b(u), b(w), b(x), b(lam), wbar, coeff_bar, d, 0.5, ws, nb, None)
+        1, b(u), b(w), b(x), b(lam), wbar, coeff_bar, d, 0.5, None, ws, nb, None)
     assert call(wbar=None, coeff_bar=None) == code("STENCIL_E_NULL")
     assert call(ws=None) == code("STENCIL_E_WORKSPACE")
     assert call(nb=need - 8) == code("STENCIL_E_WORKSPACE")
@@ -387,3 +387,60 @@ def test_boundary_option_and_halo_update_validation(L):
     items = batch_items([(16, 12, 8)])
     assert L.stencil_step_batched(1, 1, items, BASE + (64 << 32), 1 << 20, b(o), None) == code(
         "STENCIL_E_UNSUPPORTED")
+
+
+def test_generalised_diffusion_validation(L):
+    """hdiff_form and coeff_field: unknown forms, coefficient fields of the
+    wrong size or overlapping an output, and the forms without a kernel
+    (PLAIN, long columns, batched) are refused before any device work."""
+    b = ctypes.byref
+    u, data, w, out, d = fields()
+    o = _lib.StencilOptions()
+    o.hdiff_form = 3
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    o.hdiff_form = _lib.HDIFF_DAMPING
+    o.impl = _lib.IMPL_PLAIN
+    o.workspace = BASE + (40 << 32)
+    o.workspace_bytes = 1 << 30
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_UNSUPPORTED")
+    assert L.stencil_hdiff(1, b(u), b(out), d, 0.025, None, b(o), None) == code("STENCIL_E_UNSUPPORTED")
+    o = _lib.StencilOptions()
+    o.hdiff_form = _lib.HDIFF_DAMPING
+    lu, ldata, lw, lout, ld = fields(16, 12, 145)
+    assert step(L, lu, ldata, lw, lout, ld, opts=o) == code("STENCIL_E_UNSUPPORTED")  # FP64 nk > 144
+    kap = fld(16, 12, 8, halo=0, base=BASE + (41 << 32))
+    o.coeff_field = ctypes.pointer(kap)
+    small = fld(15, 12, 8, halo=0, base=BASE + (41 << 32))
+    o2 = _lib.StencilOptions()
+    o2.coeff_field = ctypes.pointer(small)
+    assert step(L, u, data, w, out, d, opts=o2) == code("STENCIL_E_SHAPE")
+    inside = fld(16, 12, 8, halo=0, base=out.data)
+    o3 = _lib.StencilOptions()
+    o3.coeff_field = ctypes.pointer(inside)
+    assert step(L, u, data, w, out, d, opts=o3) == code("STENCIL_E_ALIAS")
+    assert L.stencil_hdiff(1, b(u), b(out), d, 0.025, None, b(o3), None) == code("STENCIL_E_ALIAS")
+    ub = fld(16, 12, 8, base=out.data)
+    assert L.stencil_hdiff_adjoint(1, b(data), BASE + (42 << 32), b(ub), d, 0.025, b(o3), None) == code(
+        "STENCIL_E_ALIAS")
+    items = batch_items([(16, 12, 8)])
+    assert L.stencil_step_batched(1, 1, items, BASE + (64 << 32), 1 << 20, b(o), None) == code(
+        "STENCIL_E_UNSUPPORTED")
+    # the parameter adjoint: no scalar coeff_bar for a coefficient field
+    lam = fld(16, 12, 8, halo=0, base=BASE + (5 << 32))
+    x = fld(16, 12, 8, halo=0, base=BASE + (6 << 32))
+    wb = fld(16, 12, 8, halo=0, kextra=1, base=BASE + (7 << 32))
+    ws = BASE + (9 << 32)
+    need = L.stencil_param_workspace_bytes(1, d)
+    assert L.stencil_step_param_adjoint(1, b(u), b(w), b(x), b(lam), b(wb), BASE + (8 << 32), d, 0.5, b(o),
+                                        ws, need, None) == code("STENCIL_E_ARG")
+    # the coefficient-field gradient
+    kb = fld(16, 12, 8, halo=0, base=BASE + (43 << 32))
+    assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), None, d, None, None) == code("STENCIL_E_NULL")
+    kb_in = fld(16, 12, 8, halo=0, base=lam.data)
+    assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), b(kb_in), d, None, None) == code("STENCIL_E_ALIAS")
+    kb_short = fld(16, 12, 7, halo=0, base=BASE + (43 << 32))
+    assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), b(kb_short), d, None, None) == code("STENCIL_E_SHAPE")
+    assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), b(kb), _lib.domain3((0, 12, 8)), None, None) == 0
+    bad = _lib.StencilOptions()
+    bad.hdiff_form = -1
+    assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), b(kb), d, b(bad), None) == code("STENCIL_E_ARG")
