@@ -330,6 +330,24 @@ def main():
         out["python_call_us"] = round(host_call * 1e6, 2)
         del u_a, u_b, data, w, mask, xb, ub, db
 
+    # ------------------------------------------------ the frontend's generated step
+    if not args.only_step:
+        print("bench: the step written in the stencil language (generated HIP)", file=sys.stderr, flush=True)
+        from paper_2311_08322_amd.frontend import stencils as fs
+
+        u_a, u_b, data, w = mkfields(torch.float64)
+        xo = fields.alloc(ni, nj, nk, torch.float64, dev, halo=0, fill=0.0)
+        fs.step.build("float64")
+        t_gen = time_eager(lambda: fs.step(u_a, data, w, xo, coeff=inputs.COEFF, dt_dz=inputs.DT_DZ,
+                                           domain=dims), reps=20)
+        bg = step_bytes(ni, nj, nk, 8)
+        out["frontend"] = {"ms_per_step": round(t_gen * 1e3, 4), "alg_gbs": round(bg / t_gen / 1e9, 1),
+                           "frac": round(bg / t_gen / 1e9 / PEAK_GBS, 4),
+                           "handwritten_speedup": round(t_gen / t_step, 3),
+                           "what": "stencil-language step (5 generated kernels, temporaries crossing "
+                                   "computations in HBM), same algorithmic bytes as the fused step"}
+        del u_a, u_b, data, w, xo
+
     # ------------------------------------------------ batched uneven fields
     if not args.only_step:
         print("bench: 32 uneven fields, persistent launch vs separate launches", file=sys.stderr, flush=True)

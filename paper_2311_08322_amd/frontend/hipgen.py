@@ -1,0 +1,462 @@
+"""HIP code generation for gfx950 from an analysed stencil (the backend of
+the toolchain in the GT4Py paper, Sec. 2.3).
+
+One kernel per computation, launched in program order (Sec. 2.2: the
+computations behave as if run one after the other):
+
+* PARALLEL: a workgroup of 256 lanes owns a 64 x 4 tile of the domain and
+  marches a block of levels.  Per level, each input field read at a
+  horizontal offset is staged in LDS over the box its readers need (one
+  coalesced pass), then every statement runs over its own box (the tile
+  grown by the extent the analysis found), writing temporaries into their
+  LDS boxes, with a barrier between statements.  Outputs are stored inside
+  the domain only; temporaries that cross computations also go to their
+  workspace buffer.
+* FORWARD / BACKWARD: one lane per column of the sweep's region (64 x 4
+  lanes per workgroup, rows along i for coalescing), levels visited upwards
+  or downwards; a variable written in the sweep lives in a register, and the
+  previous level's value in a second one when the sweep reads it.
+
+The generated source also holds the C ABI of ``include/gtscript_abi.h``,
+with the argument checks of the plan (field coverage, vertical ranges,
+workspace).  Arithmetic is literal: the library is built without
+floating-point contraction.
+"""
+from __future__ import annotations
+
+from . import ir
+from .analysis import Plan
+
+GEN_VERSION = 1
+TI, TJ = 64, 4
+MIN_WGS = 2048
+
+
+class CodegenError(ValueError):
+    pass
+
+
+def _c(v: float) -> str:
+    return f"((real){float(v)!r})"
+
+
+class _Gen:
+    def __init__(self, plan: Plan, dtype: str, fingerprint: str):
+        self.p = plan
+        self.real = "double" if dtype == "float64" else "float"
+        self.dtype = dtype
+        self.fp = fingerprint
+        self.hbm = [t for t in plan.temps.values() if t.storage == "hbm"]
+        # flattened block index per (computation, block)
+        self.bidx = {}
+        n = 0
+        for cp in plan.comps:
+            for bi in range(len(cp.blocks)):
+                self.bidx[(cp.index, bi)] = n
+                n += 1
+        self.nblocks = n
+
+    # ------------------------------------------------------------ helpers
+    def f_inside(self, name, i, j):
+        e = self.p.fields[name].ext
+        return f"({i} >= {e[0]} && {i} < A.ni + {e[1]} && {j} >= {e[2]} && {j} < A.nj + {e[3]})"
+
+    def t_inside(self, name, i, j):
+        e = self.p.temps[name].ext
+        return f"({i} >= {e[0]} && {i} < A.ni + {e[1]} && {j} >= {e[2]} && {j} < A.nj + {e[3]})"
+
+    def gld_field(self, name, i, j, k):
+        return (f"gld(A.f_{name}, A.f_{name}_sj, A.f_{name}_sk, {i}, {j}, {k}, "
+                f"{self.f_inside(name, i, j)})")
+
+    def gld_temp(self, name, i, j, k):
+        return (f"gld(A.t_{name}, A.t_{name}_sj, A.t_{name}_sk, {i}, {j}, {k}, "
+                f"{self.t_inside(name, i, j)})")
+
+    # ------------------------------------------------------------ expressions
+    def expr(self, e, acc):
+        if isinstance(e, ir.Const):
+            return _c(e.value)
+        if isinstance(e, ir.Scalar):
+            return f"A.s_{e.name}"
+        if isinstance(e, ir.Access):
+            return acc(e)
+        if isinstance(e, ir.Unary):
+            a = self.expr(e.a, acc)
+            return f"(-{a})" if e.op == "-" else f"(!{a})"
+        if isinstance(e, ir.Binary):
+            return f"({self.expr(e.a, acc)} {e.op} {self.expr(e.b, acc)})"
+        if isinstance(e, ir.Compare):
+            return f"({self.expr(e.a, acc)} {e.op} {self.expr(e.b, acc)})"
+        if isinstance(e, ir.BoolOp):
+            op = "&&" if e.op == "and" else "||"
+            return f"({self.expr(e.a, acc)} {op} {self.expr(e.b, acc)})"
+        if isinstance(e, ir.Ternary):
+            return (f"(({self.expr(e.cond, acc)}) ? (real)({self.expr(e.a, acc)}) : "
+                    f"(real)({self.expr(e.b, acc)}))")
+        if isinstance(e, ir.Builtin):
+            fn = {"abs": "fabs", "min": "fmin", "max": "fmax", "sqrt": "sqrt", "exp": "exp",
+                  "log": "log"}[e.name]
+            args = ", ".join(f"(real)({self.expr(a, acc)})" for a in e.args)
+            return f"{fn}({args})"
+        raise CodegenError(f"unknown expression {e!r}")
+
+    # ------------------------------------------------------------ PARALLEL
+    def parallel_kernel(self, cp):
+        p = self.p
+        lds_temps = [t for t in cp.writes if t in p.temps and cp.index in p.temps[t].read_comps]
+        lines = [f"__global__ void __launch_bounds__(256) gts_c{cp.index}(Args A) {{",
+                 "  const int tid = threadIdx.x;",
+                 f"  const int tiles_i = (A.ni + {TI - 1}) / {TI};",
+                 f"  const int i0 = (int)(blockIdx.x % tiles_i) * {TI}, j0 = (int)(blockIdx.x / tiles_i) * {TJ};",
+                 "  const int kbeg = blockIdx.y * A.kchunk, kend = min(kbeg + A.kchunk, A.nk);"]
+        boxes = {}
+        for t in lds_temps:
+            e = p.temps[t].ext
+            bi_, bj_ = TI + e[1] - e[0], TJ + e[3] - e[2]
+            boxes[("L", t)] = (e, bi_)
+            lines.append(f"  __shared__ real L_{t}[{bi_ * bj_}];")
+        for (f, dk), e in sorted(cp.staged.items()):
+            bi_, bj_ = TI + e[1] - e[0], TJ + e[3] - e[2]
+            tag = f"S_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
+            boxes[("S", f, dk)] = (e, bi_)
+            lines.append(f"  __shared__ real {tag}[{bi_ * bj_}];")
+        lines.append("  for (int k = kbeg; k < kend; ++k) {")
+        first = True
+        for bi, (_, stmts) in enumerate(cp.blocks):
+            b = self.bidx[(cp.index, bi)]
+            kw = "if" if first else "} else if"
+            first = False
+            lines.append(f"    {kw} (k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
+            staged_here = set()
+            for s in stmts:
+                for a in ir.stmt_accesses(s)[0]:
+                    if (a.name, a.offset[2]) in cp.staged:
+                        staged_here.add((a.name, a.offset[2]))
+            for (f, dk) in sorted(staged_here):
+                e, bw = boxes[("S", f, dk)]
+                bh = TJ + e[3] - e[2]
+                tag = f"S_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
+                lines += [f"      for (int e = tid; e < {bw * bh}; e += 256) {{",
+                          f"        const int gi = i0 + ({e[0]}) + e % {bw}, gj = j0 + ({e[2]}) + e / {bw};",
+                          f"        {tag}[e] = {self.gld_field(f, 'gi', 'gj', f'k + ({dk})')};",
+                          "      }"]
+            if staged_here:
+                lines.append("      __syncthreads();")
+            for s, ext in zip(stmts, cp.stmt_ext[bi]):
+                bw, bh = TI + ext[1] - ext[0], TJ + ext[3] - ext[2]
+                lines += [f"      for (int e = tid; e < {bw * bh}; e += 256) {{",
+                          f"        const int li = e % {bw}, lj = e / {bw};",
+                          f"        const int pi = i0 + ({ext[0]}) + li, pj = j0 + ({ext[2]}) + lj;"]
+                self._check_if_offsets(s)
+
+                def acc(a, boxes=boxes):
+                    di, dj, dk = a.offset
+                    if a.name in p.fields:
+                        if ("S", a.name, dk) in boxes:
+                            e, bw_ = boxes[("S", a.name, dk)]
+                            tag = f"S_{a.name}_{'m' if dk < 0 else 'p'}{abs(dk)}"
+                            return f"{tag}[(pi + ({di}) - i0 - ({e[0]})) + (pj + ({dj}) - j0 - ({e[2]})) * {bw_}]"
+                        return self.gld_field(a.name, "pi", "pj", f"k + ({dk})")
+                    if ("L", a.name) in boxes:
+                        e, bw_ = boxes[("L", a.name)]
+                        return f"L_{a.name}[(pi + ({di}) - i0 - ({e[0]})) + (pj + ({dj}) - j0 - ({e[2]})) * {bw_}]"
+                    t = p.temps[a.name]
+                    if t.storage != "hbm":
+                        raise CodegenError(f"{a.name} read outside its computation")
+                    return self.gld_temp(a.name, f"pi + ({di})", f"pj + ({dj})", f"k + ({dk})")
+
+                def store(name, v, boxes=boxes):
+                    out = []
+                    if name in p.fields:
+                        out.append(f"if (pi >= 0 && pi < A.ni && pj >= 0 && pj < A.nj) "
+                                   f"A.f_{name}[(int64_t)pi + (int64_t)pj * A.f_{name}_sj + (int64_t)k * A.f_{name}_sk] = {v};")
+                    else:
+                        if ("L", name) in boxes:
+                            e, bw_ = boxes[("L", name)]
+                            out.append(f"L_{name}[(pi - i0 - ({e[0]})) + (pj - j0 - ({e[2]})) * {bw_}] = {v};")
+                        if p.temps[name].storage == "hbm":
+                            out.append(f"if ({self.t_inside(name, 'pi', 'pj')}) A.t_{name}[(int64_t)pi + "
+                                       f"(int64_t)pj * A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
+                    return out
+
+                lines += ["        " + l for l in self.stmt_code(s, acc, store)]
+                lines += ["      }", "      __syncthreads();"]
+        lines += ["    }", "  }", "}"]
+        return "\n".join(lines)
+
+    def _check_if_offsets(self, s):
+        if not isinstance(s, ir.If):
+            return
+        _, writes = ir.stmt_accesses(s)
+        reads, _ = ir.stmt_accesses(s)
+        for a in reads:
+            if a.name in writes and (a.offset[0], a.offset[1]) != (0, 0):
+                raise CodegenError(f"{a.name} is written inside an if and read there at a horizontal offset")
+
+    def stmt_code(self, s, acc, store):
+        if isinstance(s, ir.Assign):
+            v = self.expr(s.value, acc)
+            return ["{", f"  const real v_ = (real)({v});"] + ["  " + l for l in store(s.target, "v_")] + ["}"]
+        out = [f"if ({self.expr(s.cond, acc)}) {{"]
+        for t in s.then:
+            out += ["  " + l for l in self.stmt_code(t, acc, store)]
+        out.append("} else {")
+        for t in s.orelse:
+            out += ["  " + l for l in self.stmt_code(t, acc, store)]
+        out.append("}")
+        return out
+
+    # ------------------------------------------------------------ FORWARD / BACKWARD
+    def sequential_kernel(self, cp):
+        p = self.p
+        r = cp.region
+        wset = list(cp.writes)
+        lines = [f"__global__ void __launch_bounds__(256) gts_c{cp.index}(Args A) {{",
+                 f"  const int i = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63) + ({r[0]});",
+                 f"  const int j = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6) + ({r[2]});",
+                 f"  if (i >= A.ni + ({r[1]}) || j >= A.nj + ({r[3]})) return;"]
+        for v in wset:
+            lines.append(f"  real cur_{v} = (real)0;")
+        for v in cp.kcache:
+            lines.append(f"  real prev_{v} = (real)0;")
+        up = cp.order == ir.FORWARD
+        lines += [f"  const int klo = A.clo[{cp.index}], khi = A.chi[{cp.index}];",
+                  "  for (int s = 0; s < khi - klo; ++s) {",
+                  f"    const int k = {'klo + s' if up else 'khi - 1 - s'};",
+                  "    bool done = false;"]
+        for bi, (_, stmts) in enumerate(cp.blocks):
+            b = self.bidx[(cp.index, bi)]
+            lines.append(f"    if (!done && k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
+            lines.append("      done = true;")
+            # variables read at dk = 0 before this level assigns them: their value from memory
+            assigned = set()
+            need_init = []
+
+            def scan(stmts, assigned):
+                for s in stmts:
+                    if isinstance(s, ir.Assign):
+                        for a in ir.accesses(s.value):
+                            if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
+                                need_init.append(a.name)
+                        assigned.add(s.target)
+                    else:
+                        for a in ir.accesses(s.cond):
+                            if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
+                                need_init.append(a.name)
+                        t_set, e_set = set(assigned), set(assigned)
+                        scan(s.then, t_set)
+                        scan(s.orelse, e_set)
+                        assigned |= (t_set & e_set)
+            scan(stmts, assigned)
+            for v in need_init:
+                if v in p.fields:
+                    lines.append(f"      cur_{v} = {self.gld_field(v, 'i', 'j', 'k')};")
+                elif p.temps[v].storage == "hbm":
+                    lines.append(f"      cur_{v} = {self.gld_temp(v, 'i', 'j', 'k')};")
+                else:
+                    raise CodegenError(f"{v} is read at a level before the sweep assigns it there")
+
+            def acc(a):
+                di, dj, dk = a.offset
+                if a.name in wset:
+                    return f"cur_{a.name}" if dk == 0 else f"prev_{a.name}"
+                if a.name in p.fields:
+                    return self.gld_field(a.name, f"i + ({di})", f"j + ({dj})", f"k + ({dk})")
+                t = p.temps[a.name]
+                if t.storage != "hbm":
+                    raise CodegenError(f"{a.name} read outside its computation")
+                return self.gld_temp(a.name, f"i + ({di})", f"j + ({dj})", f"k + ({dk})")
+
+            def store(name, v):
+                out = [f"cur_{name} = {v};"]
+                if name in p.fields:
+                    out.append(f"if (i >= 0 && i < A.ni && j >= 0 && j < A.nj) A.f_{name}[(int64_t)i + "
+                               f"(int64_t)j * A.f_{name}_sj + (int64_t)k * A.f_{name}_sk] = {v};")
+                elif p.temps[name].storage == "hbm":
+                    out.append(f"if ({self.t_inside(name, 'i', 'j')}) A.t_{name}[(int64_t)i + (int64_t)j * "
+                               f"A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
+                return out
+
+            for s in stmts:
+                lines += ["      " + l for l in self.stmt_code(s, acc, store)]
+            lines.append("    }")
+        if cp.kcache:
+            lines.append("    if (done) {")
+            for v in cp.kcache:
+                lines.append(f"      prev_{v} = cur_{v};")
+            lines.append("    }")
+        lines += ["  }", "}"]
+        return "\n".join(lines)
+
+    # ------------------------------------------------------------ host side
+    def host(self):
+        p = self.p
+        sd = p.sdef
+        nf, ns = len(sd.fields), len(sd.scalars)
+        L = []
+        L.append("static int bound(int nk, int none, int v, int dflt) {")
+        L.append("  int x = none ? dflt : (v >= 0 ? v : nk + v);")
+        L.append("  return x < 0 ? 0 : (x > nk ? nk : x);")
+        L.append("}")
+        L.append("static size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }")
+        # workspace
+        L.append("static size_t ws_bytes(int64_t ni, int64_t nj, int64_t nk) {")
+        L.append("  size_t b = 0;")
+        for t in self.hbm:
+            e = t.ext
+            L.append(f"  b += r256(sizeof(real) * (size_t)(ni + {e[1] - e[0]}) * (size_t)(nj + {e[3] - e[2]}) * (size_t)nk);")
+        L.append("  return b;")
+        L.append("}")
+        L.append('extern "C" size_t gts_workspace_bytes(const int64_t domain[3]) {')
+        L.append("  if (!domain || domain[0] < 0 || domain[1] < 0 || domain[2] < 0) return 0;")
+        L.append("  return ws_bytes(domain[0], domain[1], domain[2]);")
+        L.append("}")
+        sig = f"{sd.name}|{','.join(sd.fields)}|{','.join(sd.scalars)}|{self.dtype}|{self.fp}"
+        L.append(f'extern "C" const char* gts_signature(void) {{ return "{sig}"; }}')
+        L.append('extern "C" const char* gts_last_error(void) { return g_err; }')
+        L.append('extern "C" int gts_run(const gts_field* fields, int nfields, const double* scalars, int nscalars,')
+        L.append("                       const int64_t domain[3], void* workspace, size_t workspace_bytes, hipStream_t stream) {")
+        L.append("  g_err[0] = 0;")
+        L.append(f"  if (nfields != {nf}) return fail(GTS_E_ARG, \"%d fields given, the stencil takes {nf}\", nfields);")
+        L.append(f"  if (nscalars != {ns}) return fail(GTS_E_ARG, \"%d scalars given, the stencil takes {ns}\", nscalars);")
+        if nf:
+            L.append("  if (!fields) return fail(GTS_E_NULL, \"fields is NULL\");")
+        if ns:
+            L.append("  if (!scalars) return fail(GTS_E_NULL, \"scalars is NULL\");")
+        L.append("  if (!domain) return fail(GTS_E_NULL, \"domain is NULL\");")
+        L.append("  const int64_t ni = domain[0], nj = domain[1], nk = domain[2];")
+        L.append("  if (ni < 0 || nj < 0 || nk < 0 || ni > (1 << 30) || nj > (1 << 30) || nk > (1 << 30))")
+        L.append("    return fail(GTS_E_ARG, \"domain out of range\");")
+        L.append("  Args A;")
+        L.append("  memset(&A, 0, sizeof A);")
+        L.append("  A.ni = (int)ni; A.nj = (int)nj; A.nk = (int)nk;")
+        # block bounds
+        for cp in p.comps:
+            for bi, (iv, _) in enumerate(cp.blocks):
+                b = self.bidx[(cp.index, bi)]
+                s0 = 1 if iv.start is None else 0
+                s1 = 1 if iv.end is None else 0
+                L.append(f"  A.blo[{b}] = bound((int)nk, {s0}, {iv.start or 0}, 0);")
+                L.append(f"  A.bhi[{b}] = bound((int)nk, {s1}, {iv.end or 0}, (int)nk);")
+                L.append(f"  if (A.bhi[{b}] < A.blo[{b}]) A.bhi[{b}] = A.blo[{b}];")
+        # per computation: overlap check and level range
+        for cp in p.comps:
+            bs = [self.bidx[(cp.index, bi)] for bi in range(len(cp.blocks))]
+            L.append(f"  A.clo[{cp.index}] = (int)nk; A.chi[{cp.index}] = 0;")
+            for x in bs:
+                L.append(f"  if (A.blo[{x}] < A.bhi[{x}]) {{ A.clo[{cp.index}] = imin(A.clo[{cp.index}], A.blo[{x}]); "
+                         f"A.chi[{cp.index}] = imax(A.chi[{cp.index}], A.bhi[{x}]); }}")
+            for a in range(len(bs)):
+                for b2 in range(a + 1, len(bs)):
+                    x, y = bs[a], bs[b2]
+                    L.append(f"  if (A.blo[{x}] < A.bhi[{x}] && A.blo[{y}] < A.bhi[{y}] && A.blo[{x}] < A.bhi[{y}] && "
+                             f"A.blo[{y}] < A.bhi[{x}]) return fail(GTS_E_LEVELS, \"computation {cp.index}: intervals overlap\");")
+            for bi, name in cp.prev_reads:
+                x = self.bidx[(cp.index, bi)]
+                lvl = f"A.blo[{x}] - 1" if cp.order == ir.FORWARD else f"A.bhi[{x}]"
+                cov = " || ".join(f"({lvl} >= A.blo[{y}] && {lvl} < A.bhi[{y}])" for y in bs if y != x) or "false"
+                L.append(f"  if (A.blo[{x}] < A.bhi[{x}] && !({cov})) return fail(GTS_E_LEVELS, "
+                         f"\"{name}: the sweep reads a level it has not computed\");")
+        for ci, bi, name, dk in p.temp_kreads:
+            x = self.bidx[(ci, bi)]
+            L.append(f"  if (A.blo[{x}] < A.bhi[{x}] && (A.blo[{x}] + ({dk}) < 0 || A.bhi[{x}] + ({dk}) > (int)nk)) "
+                     f"return fail(GTS_E_LEVELS, \"temporary {name} read outside its levels\");")
+        L.append("  if (ni == 0 || nj == 0 || nk == 0) return GTS_OK;")
+        # fields
+        for fi, f in enumerate(sd.fields):
+            info = p.fields[f]
+            e = info.ext if info.read else (0, 0, 0, 0)
+            L.append(f"  {{ const gts_field* F = &fields[{fi}];")
+            L.append(f"    if (!F->data) return fail(GTS_E_NULL, \"field {f}: data is NULL\");")
+            L.append(f"    if (F->stride[0] != 1 || F->lo[0] < 0 || F->lo[1] < 0 || F->lo[2] < 0 || "
+                     f"F->stride[1] < F->lo[0] + F->hi[0] || F->stride[2] < F->stride[1] * (F->lo[1] + F->hi[1]))")
+            L.append(f"      return fail(GTS_E_STRIDE, \"field {f}: bad strides or extents\");")
+            L.append(f"    if (F->lo[0] < {-e[0]} || F->hi[0] < ni + {e[1]} || F->lo[1] < {-e[2]} || F->hi[1] < nj + {e[3]})")
+            L.append(f"      return fail(GTS_E_HALO, \"field {f}: needs [%lld, %lld) x [%lld, %lld)\", "
+                     f"(long long){e[0]}, (long long)(ni + {e[1]}), (long long){e[2]}, (long long)(nj + {e[3]}));")
+            if info.written:
+                L.append(f"    if (F->hi[2] < nk) return fail(GTS_E_HALO, \"field {f}: fewer than nk levels\");")
+            for ci, bi, dk in info.kreads:
+                x = self.bidx[(ci, bi)]
+                L.append(f"    if (A.blo[{x}] < A.bhi[{x}] && (A.blo[{x}] + ({dk}) < -F->lo[2] || A.bhi[{x}] + ({dk}) > F->hi[2]))")
+                L.append(f"      return fail(GTS_E_HALO, \"field {f}: levels read beyond the field\");")
+            L.append(f"    A.f_{f} = (real*)F->data; A.f_{f}_sj = F->stride[1]; A.f_{f}_sk = F->stride[2]; }}")
+        for si, s in enumerate(sd.scalars):
+            L.append(f"  A.s_{s} = (real)scalars[{si}];")
+        L.append("  const size_t need = ws_bytes(ni, nj, nk);")
+        L.append("  if (need) {")
+        L.append("    if (!workspace) return fail(GTS_E_NULL, \"workspace is NULL (%zu bytes needed)\", need);")
+        L.append("    if (workspace_bytes < need || ((uintptr_t)workspace & 255))")
+        L.append("      return fail(GTS_E_WORKSPACE, \"workspace of %zu bytes (256-byte aligned) needed\", need);")
+        L.append("  }")
+        L.append("  char* wp = (char*)workspace;")
+        for t in self.hbm:
+            e = t.ext
+            L.append(f"  A.t_{t.name}_sj = ni + {e[1] - e[0]}; A.t_{t.name}_sk = A.t_{t.name}_sj * (nj + {e[3] - e[2]});")
+            L.append(f"  A.t_{t.name} = (real*)wp + ({-e[0]}) + ({-e[2]}) * A.t_{t.name}_sj;")
+            L.append(f"  wp += r256(sizeof(real) * (size_t)A.t_{t.name}_sk * (size_t)nk);")
+        for cp in p.comps:
+            if cp.order == ir.PARALLEL:
+                L += ["  {",
+                      f"    const int tiles = (int)(((ni + {TI - 1}) / {TI}) * ((nj + {TJ - 1}) / {TJ}));",
+                      "    int kc = (int)nk;",
+                      f"    while (kc > 1 && (int64_t)tiles * ((nk + kc - 1) / kc) < {MIN_WGS}) kc = (kc + 1) / 2;",
+                      "    A.kchunk = kc;",
+                      f"    hipLaunchKernelGGL(gts_c{cp.index}, dim3(tiles, (unsigned)((nk + kc - 1) / kc)), dim3(256), 0, stream, A);",
+                      "  }"]
+            else:
+                r = cp.region
+                L += [f"  if (A.clo[{cp.index}] < A.chi[{cp.index}]) {{",
+                      f"    const int64_t W = ni + {r[1] - r[0]}, H = nj + {r[3] - r[2]};",
+                      f"    hipLaunchKernelGGL(gts_c{cp.index}, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4)), dim3(256), 0, stream, A);",
+                      "  }"]
+        L.append("  hipError_t e = hipGetLastError();")
+        L.append("  if (e != hipSuccess) return fail(GTS_E_HIP, \"launch: %s\", hipGetErrorString(e));")
+        L.append("  return GTS_OK;")
+        L.append("}")
+        return "\n".join(L)
+
+    def source(self):
+        p = self.p
+        sd = p.sdef
+        head = [f"// generated by the stencil frontend (generator version {GEN_VERSION}) from `{sd.name}`;",
+                f"// fingerprint {self.fp}, dtype {self.dtype}.  Do not edit: regenerated from the definition.",
+                "#include <hip/hip_runtime.h>",
+                "#include <math.h>",
+                "#include <stdarg.h>",
+                "#include <stdint.h>",
+                "#include <stdio.h>",
+                "#include <string.h>",
+                '#include "gtscript_abi.h"',
+                f"typedef {self.real} real;",
+                "static thread_local char g_err[512];",
+                "static int fail(int code, const char* fmt, ...) {",
+                "  va_list ap; va_start(ap, fmt); vsnprintf(g_err, sizeof g_err, fmt, ap); va_end(ap); return code;",
+                "}",
+                "static inline int imin(int a, int b) { return a < b ? a : b; }",
+                "static inline int imax(int a, int b) { return a > b ? a : b; }",
+                "__device__ __forceinline__ real gld(const real* p, int64_t sj, int64_t sk, int i, int j, int k, bool ok) {",
+                "  return ok ? p[(int64_t)i + (int64_t)j * sj + (int64_t)k * sk] : (real)0;",
+                "}",
+                "struct Args {"]
+        for f in sd.fields:
+            head.append(f"  real* f_{f}; int64_t f_{f}_sj, f_{f}_sk;")
+        for t in self.hbm:
+            head.append(f"  real* t_{t.name}; int64_t t_{t.name}_sj, t_{t.name}_sk;")
+        for s in sd.scalars:
+            head.append(f"  real s_{s};")
+        head += ["  int ni, nj, nk, kchunk;",
+                 f"  int blo[{max(1, self.nblocks)}], bhi[{max(1, self.nblocks)}];",
+                 f"  int clo[{max(1, len(p.comps))}], chi[{max(1, len(p.comps))}];",
+                 "};"]
+        body = []
+        for cp in p.comps:
+            body.append(self.parallel_kernel(cp) if cp.order == ir.PARALLEL else self.sequential_kernel(cp))
+        return "\n".join(head) + "\n\n" + "\n\n".join(body) + "\n\n" + self.host() + "\n"
+
+
+def generate(plan: Plan, dtype: str, fingerprint: str) -> str:
+    if dtype not in ("float64", "float32"):
+        raise CodegenError(f"dtype {dtype} unsupported (float64, float32)")
+    return _Gen(plan, dtype, fingerprint).source()
