@@ -101,6 +101,8 @@ class Plan:
     comps: List[CompPlan]
     # temporaries read at vertical offsets: (comp, block, name, dk)
     temp_kreads: List[Tuple[int, int, str, int]] = field(default_factory=list)
+    # computations fused into one kernel each, in program order
+    groups: List[List[int]] = field(default_factory=list)
 
 
 def _writes(stmts):
@@ -108,6 +110,78 @@ def _writes(stmts):
     for s in stmts:
         out += ir.stmt_accesses(s)[1]
     return out
+
+
+def _comp_reads(cp):
+    out = []
+    for _, stmts in cp.blocks:
+        for s in stmts:
+            out += ir.stmt_accesses(s)[0]
+    return out
+
+
+def _groups(comps, temps):
+    """Fusion of computations into kernels, in program order.  A group is a
+    run of PARALLEL computations (P), optionally followed by one sweep S
+    (FORWARD or BACKWARD) and by more sweeps (S*), every sweep on the
+    domain's columns (its region is the domain), so that a workgroup's lanes
+    are exactly its tile's columns.  Fused, the run is evaluated level by
+    level inside S's sweep, before S's block of that level.  A computation
+    joins the group only if that gives the unfused result:
+    * P and S read what earlier members wrote at dk = 0 (one level is held),
+      at horizontal offsets only if it is a temporary (LDS box of the
+      workgroup; API fields written by the run belong to other workgroups
+      off the tile), and a later P member reads no API field the run wrote;
+    * S* read what earlier members wrote at their own column (any level);
+    * no member writes a variable an earlier member reads."""
+    groups = []
+    n = len(comps)
+    i = 0
+    while i < n:
+        g = [i]
+        wr = set(comps[i].writes)
+        rd = {a.name for a in _comp_reads(comps[i])}
+        role = "P" if comps[i].order == ir.PARALLEL else "S*"
+        if role == "S*" and comps[i].region != ZERO:
+            groups.append(g)
+            i += 1
+            continue
+
+        def fits(cp, role):
+            if set(cp.writes) & rd:
+                return False
+            for a in _comp_reads(cp):
+                if a.name not in wr:
+                    continue
+                horiz = (a.offset[0], a.offset[1]) != (0, 0)
+                if role in ("P", "S"):
+                    if a.offset[2] != 0:
+                        return False
+                    if a.name not in temps and (horiz or role == "P"):
+                        return False
+                elif horiz:
+                    return False
+            return True
+
+        j = i + 1
+        while j < n:
+            cp = comps[j]
+            if cp.order == ir.PARALLEL:
+                nxt = "P" if role == "P" else None
+            else:
+                nxt = "S" if role == "P" else "S*"
+                if cp.region != ZERO:
+                    nxt = None
+            if nxt is None or not fits(cp, nxt):
+                break
+            g.append(j)
+            wr |= set(cp.writes)
+            rd |= {a.name for a in _comp_reads(cp)}
+            role = nxt
+            j += 1
+        groups.append(g)
+        i = j
+    return groups
 
 
 def analyse(sdef: ir.StencilDef) -> Plan:
@@ -178,15 +252,6 @@ def analyse(sdef: ir.StencilDef) -> Plan:
             for s in stmts:
                 check_stmt(s)
 
-    # ---- storage of temporaries
-    for t in temps.values():
-        other = t.read_comps - t.comps
-        if len(t.comps) > 1 or other:
-            t.storage = "hbm"
-        else:
-            (ci,) = tuple(t.comps)
-            t.storage = "lds" if comps[ci].order == ir.PARALLEL else "reg"
-
     # ---- extents: backwards from the outputs
     need: Dict[str, Tuple[int, int, int, int]] = {}
     for f in fields.values():
@@ -253,6 +318,25 @@ def analyse(sdef: ir.StencilDef) -> Plan:
     for f in fields.values():
         if f.read:
             f.ext = _union(ZERO, need.get(f.name)) if need.get(f.name) is not None else ZERO
+
+    # ---- kernel groups (fusion), then the storage of temporaries
+    plan.groups = _groups(comps, set(temps))
+    group_of = {}
+    for gi, g in enumerate(plan.groups):
+        for c in g:
+            group_of[c] = gi
+    for t in temps.values():
+        users = t.comps | t.read_comps
+        gs = {group_of[c] for c in users}
+        t.storage = "hbm"
+        if len(gs) == 1:
+            g = plan.groups[gs.pop()]
+            prun = [c for c in g if comps[c].order == ir.PARALLEL]
+            first_seq = [c for c in g if comps[c].order != ir.PARALLEL][:1]
+            if t.comps <= set(prun) and t.read_comps <= set(prun) | set(first_seq):
+                t.storage = "lds"
+            elif len(t.comps) == 1 and t.read_comps <= t.comps and comps[next(iter(t.comps))].order != ir.PARALLEL:
+                t.storage = "reg"
     for t in temps.values():
         if t.storage == "hbm":
             t.ext = _union(t.ext, ZERO)

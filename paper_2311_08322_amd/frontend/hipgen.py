@@ -27,13 +27,21 @@ from __future__ import annotations
 from . import ir
 from .analysis import Plan
 
-GEN_VERSION = 1
+GEN_VERSION = 2
 TI, TJ = 64, 4
 MIN_WGS = 2048
 
 
 class CodegenError(ValueError):
     pass
+
+
+def _reads(cp):
+    out = []
+    for _, stmts in cp.blocks:
+        for s in stmts:
+            out += ir.stmt_accesses(s)[0]
+    return out
 
 
 def _c(v: float) -> str:
@@ -101,95 +109,105 @@ class _Gen:
             return f"{fn}({args})"
         raise CodegenError(f"unknown expression {e!r}")
 
-    # ------------------------------------------------------------ PARALLEL
-    def parallel_kernel(self, cp):
+    # ------------------------------------------------------------ PARALLEL parts
+    def _stag(self, ci, f, dk):
+        return f"S{ci}_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
+
+    def tile_decls(self, pruns, lds_names):
+        """LDS boxes of a tile kernel: the temporaries the run keeps on chip
+        and the staged input boxes of every run member."""
         p = self.p
-        lds_temps = [t for t in cp.writes if t in p.temps and cp.index in p.temps[t].read_comps]
-        lines = [f"__global__ void __launch_bounds__(256) gts_c{cp.index}(Args A) {{",
-                 "  const int tid = threadIdx.x;",
-                 f"  const int tiles_i = (A.ni + {TI - 1}) / {TI};",
-                 f"  const int i0 = (int)(blockIdx.x % tiles_i) * {TI}, j0 = (int)(blockIdx.x / tiles_i) * {TJ};",
-                 "  const int kbeg = blockIdx.y * A.kchunk, kend = min(kbeg + A.kchunk, A.nk);"]
-        boxes = {}
-        for t in lds_temps:
+        boxes, lines = {}, []
+        for t in lds_names:
             e = p.temps[t].ext
-            bi_, bj_ = TI + e[1] - e[0], TJ + e[3] - e[2]
-            boxes[("L", t)] = (e, bi_)
-            lines.append(f"  __shared__ real L_{t}[{bi_ * bj_}];")
-        for (f, dk), e in sorted(cp.staged.items()):
-            bi_, bj_ = TI + e[1] - e[0], TJ + e[3] - e[2]
-            tag = f"S_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
-            boxes[("S", f, dk)] = (e, bi_)
-            lines.append(f"  __shared__ real {tag}[{bi_ * bj_}];")
-        lines.append("  for (int k = kbeg; k < kend; ++k) {")
+            bw, bh = TI + e[1] - e[0], TJ + e[3] - e[2]
+            boxes[("L", t)] = (e, bw)
+            lines.append(f"  __shared__ real L_{t}[{bw * bh}];")
+        for cp in pruns:
+            for (f, dk), e in sorted(cp.staged.items()):
+                bw, bh = TI + e[1] - e[0], TJ + e[3] - e[2]
+                boxes[("S", cp.index, f, dk)] = (e, bw)
+                lines.append(f"  __shared__ real {self._stag(cp.index, f, dk)}[{bw * bh}];")
+        return boxes, lines
+
+    def par_level(self, cp, boxes, indent):
+        """The statements of a PARALLEL computation at level k (block chain,
+        staging, one barrier after the staging and after each statement)."""
+        p = self.p
+        out = []
         first = True
         for bi, (_, stmts) in enumerate(cp.blocks):
             b = self.bidx[(cp.index, bi)]
-            kw = "if" if first else "} else if"
+            out.append(f"{'if' if first else '} else if'} (k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
             first = False
-            lines.append(f"    {kw} (k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
-            staged_here = set()
-            for s in stmts:
-                for a in ir.stmt_accesses(s)[0]:
-                    if (a.name, a.offset[2]) in cp.staged:
-                        staged_here.add((a.name, a.offset[2]))
-            for (f, dk) in sorted(staged_here):
-                e, bw = boxes[("S", f, dk)]
+            staged_here = sorted({(a.name, a.offset[2]) for s in stmts for a in ir.stmt_accesses(s)[0]
+                                  if (a.name, a.offset[2]) in cp.staged})
+            for (f, dk) in staged_here:
+                e, bw = boxes[("S", cp.index, f, dk)]
                 bh = TJ + e[3] - e[2]
-                tag = f"S_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
-                lines += [f"      for (int e = tid; e < {bw * bh}; e += 256) {{",
-                          f"        const int gi = i0 + ({e[0]}) + e % {bw}, gj = j0 + ({e[2]}) + e / {bw};",
-                          f"        {tag}[e] = {self.gld_field(f, 'gi', 'gj', f'k + ({dk})')};",
-                          "      }"]
+                out += [f"  for (int e = tid; e < {bw * bh}; e += 256) {{",
+                        f"    const int gi = i0 + ({e[0]}) + e % {bw}, gj = j0 + ({e[2]}) + e / {bw};",
+                        f"    {self._stag(cp.index, f, dk)}[e] = {self.gld_field(f, 'gi', 'gj', f'k + ({dk})')};",
+                        "  }"]
             if staged_here:
-                lines.append("      __syncthreads();")
+                out.append("  __syncthreads();")
             for s, ext in zip(stmts, cp.stmt_ext[bi]):
-                bw, bh = TI + ext[1] - ext[0], TJ + ext[3] - ext[2]
-                lines += [f"      for (int e = tid; e < {bw * bh}; e += 256) {{",
-                          f"        const int li = e % {bw}, lj = e / {bw};",
-                          f"        const int pi = i0 + ({ext[0]}) + li, pj = j0 + ({ext[2]}) + lj;"]
                 self._check_if_offsets(s)
+                bw, bh = TI + ext[1] - ext[0], TJ + ext[3] - ext[2]
+                out += [f"  for (int e = tid; e < {bw * bh}; e += 256) {{",
+                        f"    const int li = e % {bw}, lj = e / {bw};",
+                        f"    const int pi = i0 + ({ext[0]}) + li, pj = j0 + ({ext[2]}) + lj;"]
+                acc = self._tile_acc(cp.index, boxes, "pi", "pj")
+                store = self._par_store(boxes)
+                out += ["    " + l for l in self.stmt_code(s, acc, store)]
+                out += ["  }", "  __syncthreads();"]
+        if not first:
+            out.append("}")
+        return ["  " * 0 + indent + l for l in out]
 
-                def acc(a, boxes=boxes):
-                    di, dj, dk = a.offset
-                    if a.name in p.fields:
-                        if ("S", a.name, dk) in boxes:
-                            e, bw_ = boxes[("S", a.name, dk)]
-                            tag = f"S_{a.name}_{'m' if dk < 0 else 'p'}{abs(dk)}"
-                            return f"{tag}[(pi + ({di}) - i0 - ({e[0]})) + (pj + ({dj}) - j0 - ({e[2]})) * {bw_}]"
-                        return self.gld_field(a.name, "pi", "pj", f"k + ({dk})")
-                    if ("L", a.name) in boxes:
-                        e, bw_ = boxes[("L", a.name)]
-                        return f"L_{a.name}[(pi + ({di}) - i0 - ({e[0]})) + (pj + ({dj}) - j0 - ({e[2]})) * {bw_}]"
-                    t = p.temps[a.name]
-                    if t.storage != "hbm":
-                        raise CodegenError(f"{a.name} read outside its computation")
-                    return self.gld_temp(a.name, f"pi + ({di})", f"pj + ({dj})", f"k + ({dk})")
+    def _tile_acc(self, ci, boxes, I, J):
+        """Accessor inside a tile kernel at point (I, J, k): staged inputs
+        of computation ci and run temporaries from LDS, the rest from memory."""
+        p = self.p
 
-                def store(name, v, boxes=boxes):
-                    out = []
-                    if name in p.fields:
-                        out.append(f"if (pi >= 0 && pi < A.ni && pj >= 0 && pj < A.nj) "
-                                   f"A.f_{name}[(int64_t)pi + (int64_t)pj * A.f_{name}_sj + (int64_t)k * A.f_{name}_sk] = {v};")
-                    else:
-                        if ("L", name) in boxes:
-                            e, bw_ = boxes[("L", name)]
-                            out.append(f"L_{name}[(pi - i0 - ({e[0]})) + (pj - j0 - ({e[2]})) * {bw_}] = {v};")
-                        if p.temps[name].storage == "hbm":
-                            out.append(f"if ({self.t_inside(name, 'pi', 'pj')}) A.t_{name}[(int64_t)pi + "
-                                       f"(int64_t)pj * A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
-                    return out
+        def acc(a):
+            di, dj, dk = a.offset
+            if ("S", ci, a.name, dk) in boxes:
+                e, bw = boxes[("S", ci, a.name, dk)]
+                return (f"{self._stag(ci, a.name, dk)}[({I} + ({di}) - i0 - ({e[0]})) + "
+                        f"({J} + ({dj}) - j0 - ({e[2]})) * {bw}]")
+            if a.name in p.fields:
+                return self.gld_field(a.name, f"{I} + ({di})", f"{J} + ({dj})", f"k + ({dk})")
+            if ("L", a.name) in boxes and dk == 0:
+                e, bw = boxes[("L", a.name)]
+                return f"L_{a.name}[({I} + ({di}) - i0 - ({e[0]})) + ({J} + ({dj}) - j0 - ({e[2]})) * {bw}]"
+            if p.temps[a.name].storage != "hbm":
+                raise CodegenError(f"{a.name} read where it is not held")
+            return self.gld_temp(a.name, f"{I} + ({di})", f"{J} + ({dj})", f"k + ({dk})")
+        return acc
 
-                lines += ["        " + l for l in self.stmt_code(s, acc, store)]
-                lines += ["      }", "      __syncthreads();"]
-        lines += ["    }", "  }", "}"]
-        return "\n".join(lines)
+    def _par_store(self, boxes):
+        p = self.p
+
+        def store(name, v):
+            out = []
+            if name in p.fields:
+                out.append(f"if (pi >= 0 && pi < A.ni && pj >= 0 && pj < A.nj) "
+                           f"A.f_{name}[(int64_t)pi + (int64_t)pj * A.f_{name}_sj + (int64_t)k * A.f_{name}_sk] = {v};")
+            else:
+                if ("L", name) in boxes:
+                    e, bw = boxes[("L", name)]
+                    out.append(f"L_{name}[(pi - i0 - ({e[0]})) + (pj - j0 - ({e[2]})) * {bw}] = {v};")
+                if p.temps[name].storage == "hbm":
+                    out.append(f"if ({self.t_inside(name, 'pi', 'pj')}) A.t_{name}[(int64_t)pi + "
+                               f"(int64_t)pj * A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
+            return out
+        return store
 
     def _check_if_offsets(self, s):
         if not isinstance(s, ir.If):
             return
-        _, writes = ir.stmt_accesses(s)
-        reads, _ = ir.stmt_accesses(s)
+        reads, writes = ir.stmt_accesses(s)
         for a in reads:
             if a.name in writes and (a.offset[0], a.offset[1]) != (0, 0):
                 raise CodegenError(f"{a.name} is written inside an if and read there at a horizontal offset")
@@ -207,87 +225,137 @@ class _Gen:
         out.append("}")
         return out
 
-    # ------------------------------------------------------------ FORWARD / BACKWARD
-    def sequential_kernel(self, cp):
+    # ------------------------------------------------------------ sweeps
+    def seq_decls(self, cp):
+        out = [f"real cur_{cp.index}_{v} = (real)0;" for v in cp.writes]
+        out += [f"real prev_{cp.index}_{v} = (real)0;" for v in cp.kcache]
+        return out
+
+    def seq_level(self, cp, outer_acc):
+        """The block chain of a sweep at level k for the lane's column (i, j);
+        outer_acc serves values of the fused run (None outside a tile kernel)."""
         p = self.p
-        r = cp.region
         wset = list(cp.writes)
-        lines = [f"__global__ void __launch_bounds__(256) gts_c{cp.index}(Args A) {{",
-                 f"  const int i = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63) + ({r[0]});",
-                 f"  const int j = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6) + ({r[2]});",
-                 f"  if (i >= A.ni + ({r[1]}) || j >= A.nj + ({r[3]})) return;"]
-        for v in wset:
-            lines.append(f"  real cur_{v} = (real)0;")
-        for v in cp.kcache:
-            lines.append(f"  real prev_{v} = (real)0;")
-        up = cp.order == ir.FORWARD
-        lines += [f"  const int klo = A.clo[{cp.index}], khi = A.chi[{cp.index}];",
-                  "  for (int s = 0; s < khi - klo; ++s) {",
-                  f"    const int k = {'klo + s' if up else 'khi - 1 - s'};",
-                  "    bool done = false;"]
+        c = cp.index
+        out = ["bool done = false;"]
         for bi, (_, stmts) in enumerate(cp.blocks):
-            b = self.bidx[(cp.index, bi)]
-            lines.append(f"    if (!done && k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
-            lines.append("      done = true;")
-            # variables read at dk = 0 before this level assigns them: their value from memory
-            assigned = set()
+            b = self.bidx[(c, bi)]
+            out.append(f"if (!done && k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
+            out.append("  done = true;")
             need_init = []
 
             def scan(stmts, assigned):
                 for s in stmts:
+                    reads = list(ir.accesses(s.value)) if isinstance(s, ir.Assign) else list(ir.accesses(s.cond))
+                    for a in reads:
+                        if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
+                            need_init.append(a.name)
                     if isinstance(s, ir.Assign):
-                        for a in ir.accesses(s.value):
-                            if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
-                                need_init.append(a.name)
                         assigned.add(s.target)
                     else:
-                        for a in ir.accesses(s.cond):
-                            if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
-                                need_init.append(a.name)
                         t_set, e_set = set(assigned), set(assigned)
                         scan(s.then, t_set)
                         scan(s.orelse, e_set)
                         assigned |= (t_set & e_set)
-            scan(stmts, assigned)
+            scan(stmts, set())
             for v in need_init:
                 if v in p.fields:
-                    lines.append(f"      cur_{v} = {self.gld_field(v, 'i', 'j', 'k')};")
+                    out.append(f"  cur_{c}_{v} = {self.gld_field(v, 'i', 'j', 'k')};")
                 elif p.temps[v].storage == "hbm":
-                    lines.append(f"      cur_{v} = {self.gld_temp(v, 'i', 'j', 'k')};")
+                    out.append(f"  cur_{c}_{v} = {self.gld_temp(v, 'i', 'j', 'k')};")
                 else:
                     raise CodegenError(f"{v} is read at a level before the sweep assigns it there")
 
             def acc(a):
                 di, dj, dk = a.offset
                 if a.name in wset:
-                    return f"cur_{a.name}" if dk == 0 else f"prev_{a.name}"
+                    return f"cur_{c}_{a.name}" if dk == 0 else f"prev_{c}_{a.name}"
+                if outer_acc is not None:
+                    return outer_acc(a)
                 if a.name in p.fields:
                     return self.gld_field(a.name, f"i + ({di})", f"j + ({dj})", f"k + ({dk})")
-                t = p.temps[a.name]
-                if t.storage != "hbm":
+                if p.temps[a.name].storage != "hbm":
                     raise CodegenError(f"{a.name} read outside its computation")
                 return self.gld_temp(a.name, f"i + ({di})", f"j + ({dj})", f"k + ({dk})")
 
             def store(name, v):
-                out = [f"cur_{name} = {v};"]
+                res = [f"cur_{c}_{name} = {v};"]
                 if name in p.fields:
-                    out.append(f"if (i >= 0 && i < A.ni && j >= 0 && j < A.nj) A.f_{name}[(int64_t)i + "
+                    res.append(f"if (i >= 0 && i < A.ni && j >= 0 && j < A.nj) A.f_{name}[(int64_t)i + "
                                f"(int64_t)j * A.f_{name}_sj + (int64_t)k * A.f_{name}_sk] = {v};")
                 elif p.temps[name].storage == "hbm":
-                    out.append(f"if ({self.t_inside(name, 'i', 'j')}) A.t_{name}[(int64_t)i + (int64_t)j * "
+                    res.append(f"if ({self.t_inside(name, 'i', 'j')}) A.t_{name}[(int64_t)i + (int64_t)j * "
                                f"A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
-                return out
+                return res
 
             for s in stmts:
-                lines += ["      " + l for l in self.stmt_code(s, acc, store)]
-            lines.append("    }")
+                out += ["  " + l for l in self.stmt_code(s, acc, store)]
+            out.append("}")
         if cp.kcache:
-            lines.append("    if (done) {")
+            out.append("if (done) {")
             for v in cp.kcache:
-                lines.append(f"      prev_{v} = cur_{v};")
-            lines.append("    }")
-        lines += ["  }", "}"]
-        return "\n".join(lines)
+                out.append(f"  prev_{c}_{v} = cur_{c}_{v};")
+            out.append("}")
+        return out
+
+    def sweep_loop(self, cp, body, lo, hi):
+        up = cp.order == ir.FORWARD
+        return ([f"for (int s = 0; s < ({hi}) - ({lo}); ++s) {{",
+                 f"  const int k = {f'({lo}) + s' if up else f'({hi}) - 1 - s'};"]
+                + ["  " + l for l in body] + ["}"])
+
+    # ------------------------------------------------------------ kernels
+    def group_kernel(self, gi, g):
+        p = self.p
+        members = [p.comps[c] for c in g]
+        prun = [cp for cp in members if cp.order == ir.PARALLEL]
+        seqs = [cp for cp in members if cp.order != ir.PARALLEL]
+        L = [f"__global__ void __launch_bounds__(256) gts_g{gi}(Args A) {{"]
+        if not prun:
+            # sweeps only: one lane per column of the region
+            r = seqs[0].region
+            L += [f"  const int i = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63) + ({r[0]});",
+                  f"  const int j = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6) + ({r[2]});",
+                  f"  if (i >= A.ni + ({r[1]}) || j >= A.nj + ({r[3]})) return;"]
+            for cp in seqs:
+                L += ["  " + l for l in self.seq_decls(cp)]
+                body = self.seq_level(cp, None)
+                L += ["  " + l for l in self.sweep_loop(cp, body, f"A.clo[{cp.index}]", f"A.chi[{cp.index}]")]
+            L.append("}")
+            return "\n".join(L)
+        # the run's temporaries held in LDS: those read by the run or the first sweep
+        readers = {a.name for cp in prun + seqs[:1] for a in _reads(cp)}
+        lds = [t for cp in prun for t in cp.writes if t in p.temps and t in readers]
+        lds = list(dict.fromkeys(lds))
+        boxes, decls = self.tile_decls(prun, lds)
+        L += ["  const int tid = threadIdx.x;",
+              f"  const int tiles_i = (A.ni + {TI - 1}) / {TI};",
+              f"  const int i0 = (int)(blockIdx.x % tiles_i) * {TI}, j0 = (int)(blockIdx.x / tiles_i) * {TJ};"]
+        L += decls
+        if not seqs:
+            L += ["  const int kbeg = blockIdx.y * A.kchunk, kend = min(kbeg + A.kchunk, A.nk);",
+                  "  for (int k = kbeg; k < kend; ++k) {"]
+            for cp in prun:
+                L += self.par_level(cp, boxes, "    ")
+            L += ["  }", "}"]
+            return "\n".join(L)
+        S = seqs[0]
+        L += [f"  const int i = i0 + (tid & {TI - 1}), j = j0 + tid / {TI};",
+              "  const bool act = i < A.ni && j < A.nj;"]
+        for cp in seqs:
+            L += ["  " + l for l in self.seq_decls(cp)]
+        body = []
+        for cp in prun:
+            body += self.par_level(cp, boxes, "")
+        inner = self.seq_level(S, self._tile_acc(-1, boxes, "i", "j"))
+        body += ["if (act) {"] + ["  " + l for l in inner] + ["}", "__syncthreads();"]
+        L += ["  " + l for l in self.sweep_loop(S, body, f"A.glo[{gi}]", f"A.ghi[{gi}]")]
+        for cp in seqs[1:]:
+            inner = self.seq_level(cp, None)
+            L += ["  if (act) {"] + ["    " + l for l in self.sweep_loop(cp, inner, f"A.clo[{cp.index}]",
+                                                                          f"A.chi[{cp.index}]")] + ["  }"]
+        L.append("}")
+        return "\n".join(L)
 
     # ------------------------------------------------------------ host side
     def host(self):
@@ -396,20 +464,34 @@ class _Gen:
             L.append(f"  A.t_{t.name}_sj = ni + {e[1] - e[0]}; A.t_{t.name}_sk = A.t_{t.name}_sj * (nj + {e[3] - e[2]});")
             L.append(f"  A.t_{t.name} = (real*)wp + ({-e[0]}) + ({-e[2]}) * A.t_{t.name}_sj;")
             L.append(f"  wp += r256(sizeof(real) * (size_t)A.t_{t.name}_sk * (size_t)nk);")
-        for cp in p.comps:
-            if cp.order == ir.PARALLEL:
+        for gi, g in enumerate(p.groups):
+            members = [p.comps[c] for c in g]
+            prun = [cp for cp in members if cp.order == ir.PARALLEL]
+            seqs = [cp for cp in members if cp.order != ir.PARALLEL]
+            if prun and not seqs:
                 L += ["  {",
                       f"    const int tiles = (int)(((ni + {TI - 1}) / {TI}) * ((nj + {TJ - 1}) / {TJ}));",
                       "    int kc = (int)nk;",
                       f"    while (kc > 1 && (int64_t)tiles * ((nk + kc - 1) / kc) < {MIN_WGS}) kc = (kc + 1) / 2;",
                       "    A.kchunk = kc;",
-                      f"    hipLaunchKernelGGL(gts_c{cp.index}, dim3(tiles, (unsigned)((nk + kc - 1) / kc)), dim3(256), 0, stream, A);",
+                      f"    hipLaunchKernelGGL(gts_g{gi}, dim3(tiles, (unsigned)((nk + kc - 1) / kc)), dim3(256), 0, stream, A);",
+                      "  }"]
+            elif prun:
+                sweep = [cp for cp in prun] + seqs[:1]
+                L.append(f"  A.glo[{gi}] = (int)nk; A.ghi[{gi}] = 0;")
+                for cp in sweep:
+                    L.append(f"  if (A.clo[{cp.index}] < A.chi[{cp.index}]) {{ A.glo[{gi}] = imin(A.glo[{gi}], "
+                             f"A.clo[{cp.index}]); A.ghi[{gi}] = imax(A.ghi[{gi}], A.chi[{cp.index}]); }}")
+                L += [f"  if (A.glo[{gi}] < A.ghi[{gi}] || " + " || ".join(f"A.clo[{cp.index}] < A.chi[{cp.index}]" for cp in seqs) + ") {",
+                      f"    const int tiles = (int)(((ni + {TI - 1}) / {TI}) * ((nj + {TJ - 1}) / {TJ}));",
+                      f"    hipLaunchKernelGGL(gts_g{gi}, dim3(tiles), dim3(256), 0, stream, A);",
                       "  }"]
             else:
-                r = cp.region
-                L += [f"  if (A.clo[{cp.index}] < A.chi[{cp.index}]) {{",
+                r = seqs[0].region
+                cond = " || ".join(f"A.clo[{cp.index}] < A.chi[{cp.index}]" for cp in seqs)
+                L += [f"  if ({cond}) {{",
                       f"    const int64_t W = ni + {r[1] - r[0]}, H = nj + {r[3] - r[2]};",
-                      f"    hipLaunchKernelGGL(gts_c{cp.index}, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4)), dim3(256), 0, stream, A);",
+                      f"    hipLaunchKernelGGL(gts_g{gi}, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4)), dim3(256), 0, stream, A);",
                       "  }"]
         L.append("  hipError_t e = hipGetLastError();")
         L.append("  if (e != hipSuccess) return fail(GTS_E_HIP, \"launch: %s\", hipGetErrorString(e));")
@@ -449,10 +531,9 @@ class _Gen:
         head += ["  int ni, nj, nk, kchunk;",
                  f"  int blo[{max(1, self.nblocks)}], bhi[{max(1, self.nblocks)}];",
                  f"  int clo[{max(1, len(p.comps))}], chi[{max(1, len(p.comps))}];",
+                 f"  int glo[{max(1, len(p.groups))}], ghi[{max(1, len(p.groups))}];",
                  "};"]
-        body = []
-        for cp in p.comps:
-            body.append(self.parallel_kernel(cp) if cp.order == ir.PARALLEL else self.sequential_kernel(cp))
+        body = [self.group_kernel(gi, g) for gi, g in enumerate(p.groups)]
         return "\n".join(head) + "\n\n" + "\n\n".join(body) + "\n\n" + self.host() + "\n"
 
 

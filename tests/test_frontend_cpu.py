@@ -35,12 +35,16 @@ def test_benchmark_stencil_plans():
     assert p.temps["flx"].ext == (-1, 0, 0, 0) and p.temps["fly"].ext == (0, 0, -1, 0)
     v = S.vadv.plan
     assert v.fields["w"].ext == (0, 0, 0, 0)
-    assert {t: x.storage for t, x in v.temps.items()} == {"a": "hbm", "c": "hbm", "m": "reg", "cp": "hbm",
+    # one fused kernel: the coefficient computations run inside the forward
+    # sweep (a, c in LDS); cp, dp cross into the backward sweep (memory)
+    assert v.groups == [[0, 1, 2, 3]]
+    assert {t: x.storage for t, x in v.temps.items()} == {"a": "lds", "c": "lds", "m": "reg", "cp": "hbm",
                                                          "dp": "hbm"}
     assert v.comps[2].order == F.FORWARD and set(v.comps[2].kcache) == {"cp", "dp"}
     assert v.comps[3].kcache == ["out"]
     st = S.step.plan
-    assert st.temps["h"].storage == "hbm" and st.fields["u"].ext == (-2, 2, -2, 2)
+    assert st.groups == [[0, 1, 2, 3, 4]]
+    assert st.temps["h"].storage == "lds" and st.fields["u"].ext == (-2, 2, -2, 2)
 
 
 def test_inlining_composes_offsets_and_folds_externals():
@@ -197,7 +201,7 @@ def test_generated_library_compiles_and_validates():
     assert L.gts_run(fl, 2, sc, 1, empty, None, 0, None) == 0  # nothing to do
     assert L.gts_workspace_bytes(dom) == 0  # every temporary on chip
     V = S.vadv.build("float64")
-    assert V.gts_workspace_bytes(dom) == 4 * ((16 * 12 * 4 * 8 + 255) // 256 * 256)  # a, c, cp, dp
+    assert V.gts_workspace_bytes(dom) == 2 * ((16 * 12 * 4 * 8 + 255) // 256 * 256)  # cp, dp
 
 
 def test_sweep_first_level_is_refused():
@@ -220,3 +224,51 @@ def test_sweep_first_level_is_refused():
     ws = 0x7F0000000000 + (5 << 32)
     rc = L.gts_run(fl, 2, None, 0, dom, ws, 1 << 20, None)
     assert rc == -6, L.gts_last_error()  # GTS_E_LEVELS: level 0 is not swept
+
+
+FUSION = {
+    "a sweep may read the run's temporaries at a horizontal offset": ("""
+        def st(u: Field, out: Field):
+            with computation(PARALLEL), interval(...):
+                t = u * 2.0
+            with computation(FORWARD), interval(...):
+                out = t[1, 0, 0]
+    """, [[0, 1]], {"t": "lds"}),
+    "an API field written by the run and read off-column breaks the group": ("""
+        def st(u: Field, v: Field, out: Field):
+            with computation(PARALLEL), interval(...):
+                v = u * 2.0
+            with computation(FORWARD), interval(...):
+                out = v[1, 0, 0]
+    """, [[0], [1]], {}),
+    "a run member reading a vertical neighbour of the run is split off": ("""
+        def st(u: Field, out: Field):
+            with computation(PARALLEL), interval(...):
+                t = u * 2.0
+            with computation(PARALLEL), interval(0, -1):
+                out = t[0, 0, 1]
+    """, [[0], [1]], {"t": "hbm"}),
+    "a write after a read of the group breaks it": ("""
+        def st(u: Field, w: Field, out: Field):
+            with computation(PARALLEL), interval(...):
+                out = u * 2.0 + w
+            with computation(PARALLEL), interval(...):
+                w = u * 0.5
+    """, [[0], [1]], {}),
+    "a second sweep joins when it reads the first one's column": ("""
+        def st(u: Field, out: Field):
+            with computation(FORWARD), interval(...):
+                t = u * 2.0
+            with computation(BACKWARD), interval(1, None):
+                out = t[0, 0, -1] + t
+    """, [[0, 1]], {"t": "hbm"}),
+}
+
+
+@pytest.mark.parametrize("case", list(FUSION), ids=list(FUSION))
+def test_fusion_groups(case):
+    src, groups, storage = FUSION[case]
+    st = _define(src)
+    assert st.plan.groups == groups
+    for t, where in storage.items():
+        assert st.plan.temps[t].storage == where
