@@ -344,8 +344,10 @@ def main():
         out["frontend"] = {"ms_per_step": round(t_gen * 1e3, 4), "alg_gbs": round(bg / t_gen / 1e9, 1),
                            "frac": round(bg / t_gen / 1e9 / PEAK_GBS, 4),
                            "handwritten_speedup": round(t_gen / t_step, 3),
-                           "what": "stencil-language step (5 generated kernels, temporaries crossing "
-                                   "computations in HBM), same algorithmic bytes as the fused step"}
+                           "what": "the step written in the stencil language: one generated kernel "
+                                   "(the run of parallel computations fused into the forward sweep, the "
+                                   "backward sweep appended; c' and d' through a workspace), timed "
+                                   "eagerly; the same algorithmic bytes as the fused step"}
         del u_a, u_b, data, w, xo
 
     # ------------------------------------------------ batched uneven fields

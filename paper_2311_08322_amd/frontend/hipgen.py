@@ -27,7 +27,7 @@ from __future__ import annotations
 from . import ir
 from .analysis import Plan
 
-GEN_VERSION = 2
+GEN_VERSION = 4
 TI, TJ = 64, 4
 MIN_WGS = 2048
 
@@ -109,13 +109,139 @@ class _Gen:
             return f"{fn}({args})"
         raise CodegenError(f"unknown expression {e!r}")
 
+    # ------------------------------------------------------------ level pipeline
+    def gldk_field(self, name, i, j, k, valid="true"):
+        """Load with the caller's vertical range checked too (prefetches
+        reach levels no statement reads there)."""
+        return (f"gld(A.f_{name}, A.f_{name}_sj, A.f_{name}_sk, {i}, {j}, {k}, "
+                f"({self.f_inside(name, i, j)} && ({k}) >= -A.f_{name}_klo && ({k}) < A.f_{name}_khi && ({valid})))")
+
+    def gldk_temp(self, name, i, j, k, valid="true"):
+        return (f"gld(A.t_{name}, A.t_{name}_sj, A.t_{name}_sk, {i}, {j}, {k}, "
+                f"({self.t_inside(name, i, j)} && ({k}) >= 0 && ({k}) < A.nk && ({valid})))")
+
+    class _Pipe:
+        """Registers of one level loop: for each input read at the lane's own
+        column (key (kind, name, dk)) the value of the current level, and the
+        staged boxes of the tile's inputs; the next level's are loaded at the
+        top of each level, while the current one is computed."""
+
+        def __init__(self, tag):
+            self.tag = tag
+            self.cols = []    # (kind, name, dk)
+            self.boxes = []   # (array, field, dk, ext, width, count)
+
+        def col(self, kind, name, dk):
+            key = (kind, name, dk)
+            if key not in self.cols:
+                self.cols.append(key)
+            return f"pc{self.tag}_{kind}_{name}_{'m' if dk < 0 else 'p'}{abs(dk)}"
+
+    def pipe_lines(self, pipe, I, J, kexpr, valid, which, step=0):
+        """Loads of every pipelined value for level kexpr into the `which`
+        registers (cur / nxt).  For the next level (step = +1 going up, -1
+        going down) a value the current level already holds at dk + step is
+        copied instead of loaded again."""
+        out = []
+        for (kind, name, dk) in pipe.cols:
+            r = pipe.col(kind, name, dk)
+            if step and (kind, name, dk + step) in pipe.cols:
+                out.append(f"{r}_{which} = {pipe.col(kind, name, dk + step)}_cur;")
+                continue
+            ld = (self.gldk_field(name, I, J, f"{kexpr} + ({dk})", valid) if kind == "f"
+                  else self.gldk_temp(name, I, J, f"{kexpr} + ({dk})", valid))
+            out.append(f"{r}_{which} = {ld};")
+        for (arr, f, dk, e, bw, cnt) in pipe.boxes:
+            n_it = (cnt + 255) // 256
+            for it in range(n_it):
+                el = f"(tid + {it * 256})"
+                gi, gj = f"(i0 + ({e[0]}) + {el} % {bw})", f"(j0 + ({e[2]}) + {el} / {bw})"
+                ld = self.gldk_field(f, gi, gj, f"{kexpr} + ({dk})", f"({valid}) && {el} < {cnt}")
+                out.append(f"pb_{arr}_{which}[{it}] = {ld};")
+        return out
+
+    def pipe_decls(self, pipe):
+        out = []
+        for (kind, name, dk) in pipe.cols:
+            r = pipe.col(kind, name, dk)
+            out.append(f"real {r}_cur = (real)0, {r}_nxt = (real)0;")
+        for (arr, f, dk, e, bw, cnt) in pipe.boxes:
+            n_it = (cnt + 255) // 256
+            out.append(f"real pb_{arr}_cur[{n_it}], pb_{arr}_nxt[{n_it}];")
+        return out
+
+    def pipe_rotate(self, pipe):
+        out = []
+        for (kind, name, dk) in pipe.cols:
+            r = pipe.col(kind, name, dk)
+            out.append(f"{r}_cur = {r}_nxt;")
+        for (arr, f, dk, e, bw, cnt) in pipe.boxes:
+            for it in range((cnt + 255) // 256):
+                out.append(f"pb_{arr}_cur[{it}] = pb_{arr}_nxt[{it}];")
+        return out
+
+    # ------------------------------------------------------------ LDS synchronisation
+    class _Sync:
+        """Barrier placement inside a tile kernel: a barrier goes before a
+        statement that reads LDS data written since the last barrier by
+        other lanes, or writes LDS data that other lanes wrote or read since
+        then.  Lanes map to box points by the statement's box (ext); the
+        same box and a zero offset mean the same lane."""
+        MIXED = "mixed"
+
+        def __init__(self):
+            self.dirty, self.reads = {}, {}
+
+        def copy(self):
+            c = _Gen._Sync()
+            c.dirty = dict(self.dirty)
+            c.reads = {k: set(v) for k, v in self.reads.items()}
+            return c
+
+        def need(self, reads, writes, ext):
+            for arr, off in reads:
+                d = self.dirty.get(arr)
+                if d is not None and (d != ext or off != (0, 0)):
+                    return True
+            for arr in writes:
+                d = self.dirty.get(arr)
+                if d is not None and d != ext:
+                    return True
+                for (e2, off2) in self.reads.get(arr, ()):
+                    if e2 != ext or off2 != (0, 0):
+                        return True
+            return False
+
+        def record(self, reads, writes, ext):
+            for arr, off in reads:
+                self.reads.setdefault(arr, set()).add((ext, off))
+            for arr in writes:
+                self.dirty[arr] = ext
+
+        def clear(self):
+            self.dirty, self.reads = {}, {}
+
+        @staticmethod
+        def merge(states):
+            m = _Gen._Sync()
+            for st in states:
+                for arr, d in st.dirty.items():
+                    if arr in m.dirty and m.dirty[arr] != d:
+                        m.dirty[arr] = _Gen._Sync.MIXED
+                    else:
+                        m.dirty.setdefault(arr, d)
+                for arr, rs in st.reads.items():
+                    m.reads.setdefault(arr, set()).update(rs)
+            return m
+
     # ------------------------------------------------------------ PARALLEL parts
     def _stag(self, ci, f, dk):
         return f"S{ci}_{f}_{'m' if dk < 0 else 'p'}{abs(dk)}"
 
-    def tile_decls(self, pruns, lds_names):
+    def tile_decls(self, pruns, lds_names, pipe):
         """LDS boxes of a tile kernel: the temporaries the run keeps on chip
-        and the staged input boxes of every run member."""
+        and the staged input boxes of every run member (their loads go
+        through the level pipeline)."""
         p = self.p
         boxes, lines = {}, []
         for t in lds_names:
@@ -126,48 +252,79 @@ class _Gen:
         for cp in pruns:
             for (f, dk), e in sorted(cp.staged.items()):
                 bw, bh = TI + e[1] - e[0], TJ + e[3] - e[2]
+                arr = self._stag(cp.index, f, dk)
                 boxes[("S", cp.index, f, dk)] = (e, bw)
-                lines.append(f"  __shared__ real {self._stag(cp.index, f, dk)}[{bw * bh}];")
+                lines.append(f"  __shared__ real {arr}[{bw * bh}];")
+                pipe.boxes.append((arr, f, dk, e, bw, bw * bh))
         return boxes, lines
 
-    def par_level(self, cp, boxes, indent):
-        """The statements of a PARALLEL computation at level k (block chain,
-        staging, one barrier after the staging and after each statement)."""
-        p = self.p
+    def _lds_reads(self, s, ci, boxes):
+        out = []
+        for a in ir.stmt_accesses(s)[0]:
+            di, dj, dk = a.offset
+            if ("S", ci, a.name, dk) in boxes:
+                out.append((self._stag(ci, a.name, dk), (di, dj)))
+            elif ("L", a.name) in boxes and dk == 0:
+                out.append((f"L_{a.name}", (di, dj)))
+        return out
+
+    def _lds_writes(self, s, boxes):
+        return [f"L_{w}" for w in ir.stmt_accesses(s)[1] if ("L", w) in boxes]
+
+    def par_level(self, cp, boxes, pipe, sync, written_in_group):
+        """The statements of a PARALLEL computation at level k: block chain,
+        staging from the pipeline registers, statements with the barriers
+        the sync state asks for.  Returns (lines, sync state after)."""
         out = []
         first = True
+        ends = []
         for bi, (_, stmts) in enumerate(cp.blocks):
             b = self.bidx[(cp.index, bi)]
             out.append(f"{'if' if first else '} else if'} (k >= A.blo[{b}] && k < A.bhi[{b}]) {{")
             first = False
-            staged_here = sorted({(a.name, a.offset[2]) for s in stmts for a in ir.stmt_accesses(s)[0]
+            st = sync.copy()
+            staged_here = sorted({(a.name, a.offset[2]) for s_ in stmts for a in ir.stmt_accesses(s_)[0]
                                   if (a.name, a.offset[2]) in cp.staged})
-            for (f, dk) in staged_here:
-                e, bw = boxes[("S", cp.index, f, dk)]
-                bh = TJ + e[3] - e[2]
-                out += [f"  for (int e = tid; e < {bw * bh}; e += 256) {{",
-                        f"    const int gi = i0 + ({e[0]}) + e % {bw}, gj = j0 + ({e[2]}) + e / {bw};",
-                        f"    {self._stag(cp.index, f, dk)}[e] = {self.gld_field(f, 'gi', 'gj', f'k + ({dk})')};",
-                        "  }"]
+            staged_arrs = [self._stag(cp.index, f, dk) for f, dk in staged_here]
             if staged_here:
-                out.append("  __syncthreads();")
-            for s, ext in zip(stmts, cp.stmt_ext[bi]):
-                self._check_if_offsets(s)
+                if st.need([], staged_arrs, "staging"):
+                    out.append("  __syncthreads();")
+                    st.clear()
+                for (f, dk) in staged_here:
+                    e, bw = boxes[("S", cp.index, f, dk)]
+                    cnt = bw * (TJ + e[3] - e[2])
+                    arr = self._stag(cp.index, f, dk)
+                    for it in range((cnt + 255) // 256):
+                        guard = f"if (tid + {it * 256} < {cnt}) " if (it + 1) * 256 > cnt else ""
+                        out.append(f"  {guard}{arr}[tid + {it * 256}] = pb_{arr}_cur[{it}];")
+                st.record([], staged_arrs, "staging")
+            for s_, ext in zip(stmts, cp.stmt_ext[bi]):
+                self._check_if_offsets(s_)
+                rd, wr = self._lds_reads(s_, cp.index, boxes), self._lds_writes(s_, boxes)
+                if st.need(rd, wr, ext):
+                    out.append("  __syncthreads();")
+                    st.clear()
                 bw, bh = TI + ext[1] - ext[0], TJ + ext[3] - ext[2]
+                lane = ext == (0, 0, 0, 0)
                 out += [f"  for (int e = tid; e < {bw * bh}; e += 256) {{",
                         f"    const int li = e % {bw}, lj = e / {bw};",
                         f"    const int pi = i0 + ({ext[0]}) + li, pj = j0 + ({ext[2]}) + lj;"]
-                acc = self._tile_acc(cp.index, boxes, "pi", "pj")
-                store = self._par_store(boxes)
-                out += ["    " + l for l in self.stmt_code(s, acc, store)]
-                out += ["  }", "  __syncthreads();"]
+                acc = self._tile_acc(cp.index, boxes, "pi", "pj", pipe if lane else None, written_in_group)
+                out += ["    " + l for l in self.stmt_code(s_, acc, self._par_store(boxes))]
+                out.append("  }")
+                st.record(rd, wr, ext)
+            ends.append(st)
         if not first:
+            out.append("} else {")
+            ends.append(sync.copy())
             out.append("}")
-        return ["  " * 0 + indent + l for l in out]
+        return out, _Gen._Sync.merge(ends) if ends else sync
 
-    def _tile_acc(self, ci, boxes, I, J):
-        """Accessor inside a tile kernel at point (I, J, k): staged inputs
-        of computation ci and run temporaries from LDS, the rest from memory."""
+    def _tile_acc(self, ci, boxes, I, J, pipe, written_in_group):
+        """Accessor inside a tile kernel at point (I, J, k): staged inputs of
+        computation ci and the run's temporaries from LDS; inputs at the
+        lane's own column from the pipeline (pipe given only where the point
+        is the lane's column); the rest from memory."""
         p = self.p
 
         def acc(a):
@@ -176,11 +333,15 @@ class _Gen:
                 e, bw = boxes[("S", ci, a.name, dk)]
                 return (f"{self._stag(ci, a.name, dk)}[({I} + ({di}) - i0 - ({e[0]})) + "
                         f"({J} + ({dj}) - j0 - ({e[2]})) * {bw}]")
-            if a.name in p.fields:
-                return self.gld_field(a.name, f"{I} + ({di})", f"{J} + ({dj})", f"k + ({dk})")
             if ("L", a.name) in boxes and dk == 0:
                 e, bw = boxes[("L", a.name)]
                 return f"L_{a.name}[({I} + ({di}) - i0 - ({e[0]})) + ({J} + ({dj}) - j0 - ({e[2]})) * {bw}]"
+            if pipe is not None and (di, dj) == (0, 0) and a.name not in written_in_group:
+                kind = "f" if a.name in p.fields else "t"
+                if kind == "f" or p.temps[a.name].storage == "hbm":
+                    return pipe.col(kind, a.name, dk) + "_cur"
+            if a.name in p.fields:
+                return self.gld_field(a.name, f"{I} + ({di})", f"{J} + ({dj})", f"k + ({dk})")
             if p.temps[a.name].storage != "hbm":
                 raise CodegenError(f"{a.name} read where it is not held")
             return self.gld_temp(a.name, f"{I} + ({di})", f"{J} + ({dj})", f"k + ({dk})")
@@ -231,9 +392,10 @@ class _Gen:
         out += [f"real prev_{cp.index}_{v} = (real)0;" for v in cp.kcache]
         return out
 
-    def seq_level(self, cp, outer_acc):
+    def seq_level(self, cp, outer_acc, pipe, written_in_group):
         """The block chain of a sweep at level k for the lane's column (i, j);
-        outer_acc serves values of the fused run (None outside a tile kernel)."""
+        outer_acc serves values of the fused run (None outside a tile
+        kernel), pipe the lane-column inputs."""
         p = self.p
         wset = list(cp.writes)
         c = cp.index
@@ -245,17 +407,17 @@ class _Gen:
             need_init = []
 
             def scan(stmts, assigned):
-                for s in stmts:
-                    reads = list(ir.accesses(s.value)) if isinstance(s, ir.Assign) else list(ir.accesses(s.cond))
+                for s_ in stmts:
+                    reads = list(ir.accesses(s_.value)) if isinstance(s_, ir.Assign) else list(ir.accesses(s_.cond))
                     for a in reads:
                         if a.name in wset and a.offset[2] == 0 and a.name not in assigned and a.name not in need_init:
                             need_init.append(a.name)
-                    if isinstance(s, ir.Assign):
-                        assigned.add(s.target)
+                    if isinstance(s_, ir.Assign):
+                        assigned.add(s_.target)
                     else:
                         t_set, e_set = set(assigned), set(assigned)
-                        scan(s.then, t_set)
-                        scan(s.orelse, e_set)
+                        scan(s_.then, t_set)
+                        scan(s_.orelse, e_set)
                         assigned |= (t_set & e_set)
             scan(stmts, set())
             for v in need_init:
@@ -272,6 +434,10 @@ class _Gen:
                     return f"cur_{c}_{a.name}" if dk == 0 else f"prev_{c}_{a.name}"
                 if outer_acc is not None:
                     return outer_acc(a)
+                if pipe is not None and (di, dj) == (0, 0) and a.name not in written_in_group:
+                    kind = "f" if a.name in p.fields else "t"
+                    if kind == "f" or p.temps[a.name].storage == "hbm":
+                        return pipe.col(kind, a.name, dk) + "_cur"
                 if a.name in p.fields:
                     return self.gld_field(a.name, f"i + ({di})", f"j + ({dj})", f"k + ({dk})")
                 if p.temps[a.name].storage != "hbm":
@@ -288,8 +454,8 @@ class _Gen:
                                f"A.t_{name}_sj + (int64_t)k * A.t_{name}_sk] = {v};")
                 return res
 
-            for s in stmts:
-                out += ["  " + l for l in self.stmt_code(s, acc, store)]
+            for s_ in stmts:
+                out += ["  " + l for l in self.stmt_code(s_, acc, store)]
             out.append("}")
         if cp.kcache:
             out.append("if (done) {")
@@ -298,11 +464,23 @@ class _Gen:
             out.append("}")
         return out
 
-    def sweep_loop(self, cp, body, lo, hi):
-        up = cp.order == ir.FORWARD
-        return ([f"for (int s = 0; s < ({hi}) - ({lo}); ++s) {{",
-                 f"  const int k = {f'({lo}) + s' if up else f'({hi}) - 1 - s'};"]
-                + ["  " + l for l in body] + ["}"])
+    def level_loop(self, order, lo, hi, body, pipe, I, J, valid_lane="true"):
+        """A level loop (upwards or downwards) with its register pipeline:
+        the first level's values before the loop, the next level's loaded at
+        the top of every level, rotated at its end."""
+        up = order != ir.BACKWARD
+        k0 = f"({lo})" if up else f"({hi}) - 1"
+        out = self.pipe_decls(pipe)
+        out += self.pipe_lines(pipe, I, J, k0, f"({lo}) < ({hi}) && ({valid_lane})", "cur")
+        out += [f"for (int s = 0; s < ({hi}) - ({lo}); ++s) {{",
+                f"  const int k = {f'({lo}) + s' if up else f'({hi}) - 1 - s'};",
+                f"  const int kn = {'k + 1' if up else 'k - 1'};"]
+        out += ["  " + l for l in self.pipe_lines(pipe, I, J, "kn", f"s + 1 < ({hi}) - ({lo}) && ({valid_lane})", "nxt",
+                                                  1 if up else -1)]
+        out += ["  " + l for l in body]
+        out += ["  " + l for l in self.pipe_rotate(pipe)]
+        out.append("}")
+        return out
 
     # ------------------------------------------------------------ kernels
     def group_kernel(self, gi, g):
@@ -310,6 +488,9 @@ class _Gen:
         members = [p.comps[c] for c in g]
         prun = [cp for cp in members if cp.order == ir.PARALLEL]
         seqs = [cp for cp in members if cp.order != ir.PARALLEL]
+        written = set()
+        for cp in members:
+            written |= set(cp.writes)
         L = [f"__global__ void __launch_bounds__(256) gts_g{gi}(Args A) {{"]
         if not prun:
             # sweeps only: one lane per column of the region
@@ -317,43 +498,58 @@ class _Gen:
             L += [f"  const int i = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63) + ({r[0]});",
                   f"  const int j = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6) + ({r[2]});",
                   f"  if (i >= A.ni + ({r[1]}) || j >= A.nj + ({r[3]})) return;"]
-            for cp in seqs:
+            for n, cp in enumerate(seqs):
                 L += ["  " + l for l in self.seq_decls(cp)]
-                body = self.seq_level(cp, None)
-                L += ["  " + l for l in self.sweep_loop(cp, body, f"A.clo[{cp.index}]", f"A.chi[{cp.index}]")]
+                pipe = _Gen._Pipe(f"{gi}_{n}")
+                # later sweeps of the group run after this lane finished the earlier ones
+                body = self.seq_level(cp, None, pipe, set(cp.writes) | {w for c in seqs[n + 1:] for w in c.writes})
+                L += ["  {"] + ["    " + l for l in self.level_loop(cp.order, f"A.clo[{cp.index}]", f"A.chi[{cp.index}]",
+                                                                       body, pipe, "i", "j")] + ["  }"]
             L.append("}")
             return "\n".join(L)
         # the run's temporaries held in LDS: those read by the run or the first sweep
         readers = {a.name for cp in prun + seqs[:1] for a in _reads(cp)}
-        lds = [t for cp in prun for t in cp.writes if t in p.temps and t in readers]
-        lds = list(dict.fromkeys(lds))
-        boxes, decls = self.tile_decls(prun, lds)
+        lds = list(dict.fromkeys(t for cp in prun for t in cp.writes if t in p.temps and t in readers))
+        pipe = _Gen._Pipe(f"{gi}")
+        boxes, decls = self.tile_decls(prun, lds, pipe)
         L += ["  const int tid = threadIdx.x;",
               f"  const int tiles_i = (A.ni + {TI - 1}) / {TI};",
-              f"  const int i0 = (int)(blockIdx.x % tiles_i) * {TI}, j0 = (int)(blockIdx.x / tiles_i) * {TJ};"]
-        L += decls
-        if not seqs:
-            L += ["  const int kbeg = blockIdx.y * A.kchunk, kend = min(kbeg + A.kchunk, A.nk);",
-                  "  for (int k = kbeg; k < kend; ++k) {"]
-            for cp in prun:
-                L += self.par_level(cp, boxes, "    ")
-            L += ["  }", "}"]
-            return "\n".join(L)
-        S = seqs[0]
-        L += [f"  const int i = i0 + (tid & {TI - 1}), j = j0 + tid / {TI};",
+              f"  const int i0 = (int)(blockIdx.x % tiles_i) * {TI}, j0 = (int)(blockIdx.x / tiles_i) * {TJ};",
+              f"  const int i = i0 + (tid & {TI - 1}), j = j0 + tid / {TI};",
               "  const bool act = i < A.ni && j < A.nj;"]
+        L += decls
         for cp in seqs:
             L += ["  " + l for l in self.seq_decls(cp)]
+        sync = _Gen._Sync()
         body = []
         for cp in prun:
-            body += self.par_level(cp, boxes, "")
-        inner = self.seq_level(S, self._tile_acc(-1, boxes, "i", "j"))
-        body += ["if (act) {"] + ["  " + l for l in inner] + ["}", "__syncthreads();"]
-        L += ["  " + l for l in self.sweep_loop(S, body, f"A.glo[{gi}]", f"A.ghi[{gi}]")]
-        for cp in seqs[1:]:
-            inner = self.seq_level(cp, None)
-            L += ["  if (act) {"] + ["    " + l for l in self.sweep_loop(cp, inner, f"A.clo[{cp.index}]",
-                                                                          f"A.chi[{cp.index}]")] + ["  }"]
+            lines, sync = self.par_level(cp, boxes, pipe, sync, written)
+            body += lines
+        if seqs:
+            S = seqs[0]
+            zero = (0, 0, 0, 0)
+            rd = [(f"L_{a.name}", (a.offset[0], a.offset[1])) for a in _reads(S)
+                  if ("L", a.name) in boxes and a.offset[2] == 0]
+            if sync.need(rd, [], zero):
+                body.append("__syncthreads();")
+                sync.clear()
+            inner = self.seq_level(S, self._tile_acc(-1, boxes, "i", "j", pipe, written), pipe, written)
+            body += ["if (act) {"] + ["  " + l for l in inner] + ["}"]
+        body.append("__syncthreads();")  # the next level overwrites the boxes
+        if seqs:
+            L += ["  " + l for l in self.level_loop(seqs[0].order, f"A.glo[{gi}]", f"A.ghi[{gi}]", body, pipe,
+                                                     "i", "j")]
+            for n, cp in enumerate(seqs[1:]):
+                p2 = _Gen._Pipe(f"{gi}_{n + 1}")
+                # everything earlier members wrote is complete for this column
+                # (this lane's sweep, or other lanes before the last barrier)
+                inner = self.seq_level(cp, None, p2, set(cp.writes))
+                L += ["  if (act) {"] + ["    " + l for l in self.level_loop(cp.order, f"A.clo[{cp.index}]",
+                                                                                f"A.chi[{cp.index}]", inner, p2,
+                                                                                "i", "j")] + ["  }"]
+        else:
+            L += ["  const int kbeg = blockIdx.y * A.kchunk, kend = min(kbeg + A.kchunk, A.nk);"]
+            L += ["  " + l for l in self.level_loop(ir.FORWARD, "kbeg", "kend", body, pipe, "i", "j")]
         L.append("}")
         return "\n".join(L)
 
@@ -449,7 +645,8 @@ class _Gen:
                 x = self.bidx[(ci, bi)]
                 L.append(f"    if (A.blo[{x}] < A.bhi[{x}] && (A.blo[{x}] + ({dk}) < -F->lo[2] || A.bhi[{x}] + ({dk}) > F->hi[2]))")
                 L.append(f"      return fail(GTS_E_HALO, \"field {f}: levels read beyond the field\");")
-            L.append(f"    A.f_{f} = (real*)F->data; A.f_{f}_sj = F->stride[1]; A.f_{f}_sk = F->stride[2]; }}")
+            L.append(f"    A.f_{f} = (real*)F->data; A.f_{f}_sj = F->stride[1]; A.f_{f}_sk = F->stride[2];")
+            L.append(f"    A.f_{f}_klo = F->lo[2]; A.f_{f}_khi = F->hi[2]; }}")
         for si, s in enumerate(sd.scalars):
             L.append(f"  A.s_{s} = (real)scalars[{si}];")
         L.append("  const size_t need = ws_bytes(ni, nj, nk);")
@@ -523,7 +720,7 @@ class _Gen:
                 "}",
                 "struct Args {"]
         for f in sd.fields:
-            head.append(f"  real* f_{f}; int64_t f_{f}_sj, f_{f}_sk;")
+            head.append(f"  real* f_{f}; int64_t f_{f}_sj, f_{f}_sk, f_{f}_klo, f_{f}_khi;")
         for t in self.hbm:
             head.append(f"  real* t_{t.name}; int64_t t_{t.name}_sj, t_{t.name}_sk;")
         for s in sd.scalars:
