@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only-step", action="store_true", help="time the fused forward step only")
+    ap.add_argument("--with-frontend", action="store_true",
+                    help="with --only-step: also time the step written in the stencil language")
     ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only time a plain device copy of this many MiB (counter calibration)")
@@ -331,7 +333,7 @@ def main():
         del u_a, u_b, data, w, mask, xb, ub, db
 
     # ------------------------------------------------ the frontend's generated step
-    if not args.only_step:
+    if not args.only_step or args.with_frontend:
         print("bench: the step written in the stencil language (generated HIP)", file=sys.stderr, flush=True)
         from paper_2311_08322_amd.frontend import stencils as fs
 
