@@ -312,6 +312,45 @@ def main():
                           "adj_ms": round(t_adj * 1e3, 4), "adj_gbs": round(ab / t_adj / 1e9, 1),
                           "adj_frac": round(ab / t_adj / 1e9 / PEAK_GBS, 4),
                           "fwd_mask_gbs": round(step_bytes(ni, nj, nk, 8, True) / t_fwd / 1e9, 1)}
+        # ---------------------------- the adjoint workload 256x256x80, rotating sets
+        # one set (about 170 MB) fits the 256 MB last-level cache, so R sets
+        # (> 512 MB together) are cycled and each call touches a cold set
+        print("bench: adjoint vs forward at 256x256x80 (rotating buffer sets)", file=sys.stderr, flush=True)
+        w4 = inputs.ADJ_256
+        d4 = (w4.ni, w4.nj, w4.nk)
+        f4 = inputs.fields_for(w4)
+        ob4 = inputs.cotangent(*d4)
+        sets = []
+        for _ in range(4):
+            sets.append(dict(u=fields.from_padded(f4.u, torch.float64, dev),
+                             data=fields.from_interior(f4.data, torch.float64, dev),
+                             w=fields.from_interior(f4.w, torch.float64, dev),
+                             out=fields.alloc(*d4, torch.float64, dev, halo=0, fill=0.0),
+                             mask=fields.mask_tensor(d4, dev),
+                             xb=fields.from_interior(ob4, torch.float64, dev),
+                             ub=fields.alloc(*d4, torch.float64, dev, fill=0.0),
+                             db=fields.alloc(*d4, torch.float64, dev, halo=0, fill=0.0)))
+        rot = {"n": 0}
+
+        def fwd4():
+            z = sets[rot["n"] % len(sets)]
+            rot["n"] += 1
+            api.stencil_step(z["u"], z["data"], z["w"], z["out"], d4, inputs.COEFF, inputs.DT_DZ, mask=z["mask"])
+
+        def adj4():
+            z = sets[rot["n"] % len(sets)]
+            rot["n"] += 1
+            api.stencil_step_adjoint(z["xb"], z["w"], z["mask"], z["ub"], z["db"], d4, inputs.COEFF, inputs.DT_DZ)
+
+        t_f4 = time_eager(fwd4, reps=40)
+        t_a4 = time_eager(adj4, reps=40)
+        ab4 = adjoint_bytes(*d4, 8)
+        out["adjoint_256"] = {"ratio_adj_over_fwd": round(t_a4 / t_f4, 3), "fwd_mask_ms": round(t_f4 * 1e3, 4),
+                              "adj_ms": round(t_a4 * 1e3, 4), "adj_gbs": round(ab4 / t_a4 / 1e9, 1),
+                              "adj_frac": round(ab4 / t_a4 / 1e9 / PEAK_GBS, 4),
+                              "what": "step adjoint (with data_bar) vs forward step saving the mask, "
+                                      "256x256x80 FP64, 4 rotating buffer sets of ~170 MB"}
+        del sets
         # ------------------------------------------------ plain per-stage chain
         print("bench: plain per-stage kernels", file=sys.stderr, flush=True)
         po = api.Options(impl=api.IMPL_PLAIN)
