@@ -99,8 +99,9 @@ struct MaskRec {
 
 template <typename T, int TI, int TJ>
 struct SplitSmem {
-  T su[2][2][TileAddr<T, TI, TJ>::NLD * kWG];  // [half][step parity]
-  T xch[2][2][kWG];                            // innermost (e, f) of each half and column
+  static constexpr int NT = TI * TJ;          // columns of the tile (lanes per half)
+  T su[2][2][TileAddr<T, TI, TJ>::NLD * NT];  // [half][step parity]
+  T xch[2][2][NT];                            // innermost (e, f) of each half and column
 };
 
 // VAR: the generalised diffusion (per-point coefficient when A.kappa is
@@ -109,7 +110,7 @@ template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL, bool 
 __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, SplitSmem<T, TI, TJ>& sm) {
   using TA = TileAddr<T, TI, TJ>;
   constexpr int NT = TA::NT, HI = TA::HI, NLD = TA::NLD;
-  static_assert(NT == kWG, "tile must hold 256 columns");
+  static_assert(NT == 256 || NT == 128, "a tile holds 256 or 128 columns");
 
   const int half = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // 0: top, 1: bottom
   const int ltid = threadIdx.x - half * NT;

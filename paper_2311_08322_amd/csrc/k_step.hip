@@ -13,21 +13,25 @@ static hipError_t step_by_tile(const StepArgs<T>& A, int tile_i, hipStream_t s) 
 
 template <typename T>
 hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) {
+  const bool var = A.kappa != nullptr || A.form != 0;  // the generalised diffusion: two-ended step only
+  if (var || (col == 3 && A.nk <= split_step_limit(sizeof(T)))) {  // STENCIL_COLUMN_SPLIT
+    if (A.nk > split_step_limit(sizeof(T))) return hipErrorInvalidValue;
+    constexpr int NT = GT4MI_SPLIT_NT;
+    const int tj = NT / tile_i;
+    A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+    A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
+    if (var) {
+      if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, true>(A, s);
+      if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, true>(A, s);
+      return launch_split_classes<T, 16, NT / 16, true>(A, s);
+    }
+    if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, false>(A, s);
+    if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, false>(A, s);
+    return launch_split_classes<T, 16, NT / 16, false>(A, s);
+  }
   const int tj = kWG / tile_i;
   A.tiles_i = (A.ni + tile_i - 1) / tile_i;
   A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
-  if (A.kappa != nullptr || A.form != 0) {
-    // the generalised diffusion is built for the two-ended step only
-    if (A.nk > split_step_limit(sizeof(T))) return hipErrorInvalidValue;
-    if (tile_i == 64) return launch_split_classes<T, 64, 4, true>(A, s);
-    if (tile_i == 32) return launch_split_classes<T, 32, 8, true>(A, s);
-    return launch_split_classes<T, 16, 16, true>(A, s);
-  }
-  if (col == 3 && A.nk <= split_step_limit(sizeof(T))) {  // STENCIL_COLUMN_SPLIT
-    if (tile_i == 64) return launch_split_classes<T, 64, 4, false>(A, s);
-    if (tile_i == 32) return launch_split_classes<T, 32, 8, false>(A, s);
-    return launch_split_classes<T, 16, 16, false>(A, s);
-  }
   if constexpr (sizeof(T) == 4) {
     // binary32 columns up to the largest class fit their registers
     (void)col;

@@ -15,11 +15,11 @@ namespace gt4mi {
 template hipError_t launch_column_split_classes<GT4MI_T, GT4MI_ADJ>(StepArgs<GT4MI_T>, hipStream_t);
 #elif defined(GT4MI_SPLIT)
 #ifdef GT4MI_VAR
-template hipError_t launch_split_classes<GT4MI_T, GT4MI_TI, 256 / GT4MI_TI, true>(const StepArgs<GT4MI_T>&,
-                                                                                  hipStream_t);
+template hipError_t launch_split_classes<GT4MI_T, GT4MI_TI, GT4MI_SPLIT_NT / GT4MI_TI, true>(
+    const StepArgs<GT4MI_T>&, hipStream_t);
 #else
-template hipError_t launch_split_classes<GT4MI_T, GT4MI_TI, 256 / GT4MI_TI, false>(const StepArgs<GT4MI_T>&,
-                                                                                   hipStream_t);
+template hipError_t launch_split_classes<GT4MI_T, GT4MI_TI, GT4MI_SPLIT_NT / GT4MI_TI, false>(
+    const StepArgs<GT4MI_T>&, hipStream_t);
 #endif
 #elif defined(GT4MI_VADV)
 template hipError_t launch_vadv_classes<GT4MI_T, GT4MI_COL>(const StepArgs<GT4MI_T>&, hipStream_t);

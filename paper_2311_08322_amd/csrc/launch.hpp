@@ -26,6 +26,12 @@ hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, bool ADJ>
 hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s);
 constexpr int column_split_limit(int elem_bytes) { return elem_bytes == 8 ? 144 : 160; }
+// Columns per tile of the two-ended fused step (two lanes per column): 256
+// makes 512-lane workgroups, 128 makes 256-lane ones, of which two fit a CU
+// at the register use of the longer classes.
+#ifndef GT4MI_SPLIT_NT
+#define GT4MI_SPLIT_NT 256
+#endif
 // two-ended fused step (k_split.hpp): nk <= 144 (FP64) / 160 (FP32)
 constexpr int split_step_limit(int elem_bytes) { return elem_bytes == 8 ? 144 : 160; }
 template <typename T>
