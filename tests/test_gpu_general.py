@@ -214,3 +214,53 @@ def test_general_graph_matches_eager():
             assert np.array_equal(host(fields.padded(u_a, ni, nj, nk)), eager)
     finally:
         api.stencil_graph_destroy(g)
+
+
+def test_autograd_step_with_field_and_damping():
+    """autograd.step with a per-point coefficient tensor and the damping
+    form: the gradients are the adjoint entry points' (bit for bit) and match
+    the oracle's (kappa_bar = -lam D(u), lam = T^-T x_bar)."""
+    from paper_2311_08322_amd import autograd
+    ni, nj, nk = 40, 24, 12
+    dims = (ni, nj, nk)
+    f = inputs.fields_sized(ni, nj, nk, seed=606)
+    k = inputs.coeff_field(ni, nj, nk)
+    dt = torch.float64
+    u = torch.tensor(f.u, dtype=dt, device=DEV, requires_grad=True)
+    data = torch.tensor(f.data, dtype=dt, device=DEV, requires_grad=True)
+    w = torch.tensor(f.w, dtype=dt, device=DEV, requires_grad=True)
+    kap = torch.tensor(k, dtype=dt, device=DEV, requires_grad=True)
+    ob = inputs.cotangent(ni, nj, nk)
+    x = autograd.step(u, data, w, kap, inputs.DT_DZ, damping=True)
+    (x * torch.tensor(ob, dtype=dt, device=DEV)).sum().backward()
+    nxt, mx, my = orc.step(f.u, f.data, f.w, 0.0, inputs.DT_DZ, kappa=k, damping=True)
+    assert rel_err(host(x), nxt[:, 2:-2, 2:-2]) <= 1e-12
+    lam = orc.vadv_adjoint(ob, f.w, inputs.DT_DZ)
+    assert rel_err(host(data.grad), lam) <= 1e-12
+    ubr = orc.hdiff_adjoint(lam, mx, my, 0.0, kappa=k, damping=True)
+    assert rel_err(host(u.grad), ubr) <= 1e-12
+    assert rel_err(host(kap.grad), orc.coeff_field_grad(f.u, lam, mx, my, damping=True)) <= 1e-12
+    assert rel_err(host(w.grad), orc.w_grad(f.w, nxt[:, 2:-2, 2:-2], lam, inputs.DT_DZ)) <= 1e-12
+
+
+@pytest.mark.parametrize("field", [False, True], ids=["scalar", "field"])
+def test_autograd_hdiff_coefficient_gradient(field):
+    from paper_2311_08322_amd import autograd
+    ni, nj, nk = 37, 29, 5
+    f = inputs.fields_sized(ni, nj, nk, seed=607)
+    k = inputs.coeff_field(ni, nj, nk)
+    dt = torch.float64
+    u = torch.tensor(f.u, dtype=dt, device=DEV, requires_grad=True)
+    c = torch.tensor(k if field else inputs.COEFF, dtype=dt, device=DEV, requires_grad=True)
+    ob = inputs.cotangent(ni, nj, nk)
+    out = autograd.hdiff(u, c, damping=True)
+    (out * torch.tensor(ob, dtype=dt, device=DEV)).sum().backward()
+    mx, my = orc.hdiff_masks(f.u, damping=True)
+    want_u = orc.hdiff_adjoint(ob, mx, my, inputs.COEFF, kappa=k if field else None, damping=True)
+    assert rel_err(host(u.grad), want_u) <= 1e-12
+    if field:
+        assert rel_err(host(c.grad), orc.coeff_field_grad(f.u, ob, mx, my, damping=True)) <= 1e-12
+    else:
+        g = orc.coeff_grad(f.u, ob, mx, my, damping=True)
+        scale = float(np.sum(np.abs(orc.coeff_field_grad(f.u, ob, mx, my, damping=True))))
+        assert abs(float(c.grad.item()) - g) <= 1e-12 * scale
