@@ -99,7 +99,6 @@ class StencilObject:
         self.definition = parse_stencil(fn, self.externals, _functions_visible(fn))
         self.plan = analyse(self.definition)
         self._libs = {}
-        self._ws = {}
 
     @property
     def name(self):
@@ -175,19 +174,21 @@ class StencilObject:
         sc = (ctypes.c_double * max(1, len(sd.scalars)))(*[float(scalars[s]) for s in sd.scalars])
         dom = (ctypes.c_int64 * 3)(*domain)
         nb = L.gts_workspace_bytes(dom)
+        if stream is None:
+            ts = torch.cuda.current_stream() if torch.cuda.is_available() else None
+        elif isinstance(stream, int):
+            ts = torch.cuda.ExternalStream(stream)
+        else:
+            ts = stream
+        s = ts.cuda_stream if ts is not None else None
         ws = None
         if nb:
-            dev = fl[0][1].device
-            key = (dts, dev, nb)
-            ws = self._ws.get(key)
-            if ws is None:
-                ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
-                self._ws = {key: ws}  # keep one workspace per stencil object
+            # one workspace per call from torch's caching allocator, tied to the
+            # stream the kernels run on (overlapping calls never share one)
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device=fl[0][1].device)
+            if ts is not None and ts != torch.cuda.current_stream():
+                ws.record_stream(ts)
         wp = 0 if ws is None else (ws.data_ptr() + 255) // 256 * 256
-        if stream is None:
-            s = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
-        else:
-            s = stream if isinstance(stream, int) else stream.cuda_stream
         rc = L.gts_run(arr, len(fl), sc, len(sd.scalars), dom, wp or None, nb, s)
         if rc != 0:
             raise StencilRunError(rc, L.gts_last_error().decode(errors="replace"))

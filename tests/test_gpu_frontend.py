@@ -108,3 +108,24 @@ def test_refused_call_raises():
     out = fields.alloc(ni, nj, nk, torch.float64, DEV, halo=0, fill=0.0)
     with pytest.raises(StencilRunError):
         S.hdiff(u, out, coeff=0.025, domain=(ni, nj, nk))
+
+
+def test_step_on_two_streams():
+    """The generated step on two side streams at once (each call with its own
+    workspace) equals the default-stream result bit for bit."""
+    ni, nj, nk = 96, 64, 40
+    dims = (ni, nj, nk)
+    f = inputs.fields_sized(ni, nj, nk, seed=704)
+    u, data, w = dev_fields(f, torch.float64, DEV)
+    ref = fields.alloc(ni, nj, nk, torch.float64, DEV, halo=0, fill=0.0)
+    S.step(u, data, w, ref, coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, domain=dims)
+    outs = [fields.alloc(ni, nj, nk, torch.float64, DEV, halo=0, fill=0.0) for _ in range(2)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    torch.cuda.synchronize()
+    for o, s in zip(outs, streams):
+        for _ in range(3):
+            S.step(u, data, w, o, coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, domain=dims, stream=s)
+    torch.cuda.synchronize()
+    want = host(fields.interior(ref, ni, nj, nk))
+    for o in outs:
+        assert np.array_equal(host(fields.interior(o, ni, nj, nk)), want)
