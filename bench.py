@@ -235,12 +235,11 @@ def main():
 
     # ------------------------------------------------------------ autotuning
     # the library's autotuner picks tile and column store for this size class
-    print("bench: autotuning the fused step and adjoint", file=sys.stderr, flush=True)
+    print("bench: autotuning the fused step", file=sys.stderr, flush=True)
     tuned = {}
     for dt, name in ((api.F64, "f64"), (api.F32, "f32")):
         api.stencil_autotune(dt, api.OP_STEP, dims, reps=3)
         tuned[name] = api.stencil_tuning_lookup(dt, api.OP_STEP, dims)
-    api.stencil_autotune(api.F64, api.OP_STEP_ADJOINT, dims, reps=3)
 
     # ---------------------------------------------------------------- FP64 step
     print(f"bench: fused step {dims} fp64, {K} steps per graph, {args.reps} replays", file=sys.stderr,

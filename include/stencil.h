@@ -127,8 +127,10 @@ typedef enum {
 
 typedef struct {
   int32_t impl;         /* stencil_impl */
-  int32_t tile_i;       /* horizontal tile of the fused kernels; 0 = tuned */
-  int32_t tile_j;       /*   supported: 64x4, 32x8, 16x16 */
+  int32_t tile_i;       /* horizontal tile of the fused forward kernels (hdiff, */
+  int32_t tile_j;       /*   step, batched step); 0 = tuned; supported: 64x4,
+                           32x8, 16x16.  The adjoints' gather walks fixed strips
+                           and ignores it (the value is still validated). */
   int32_t column_store; /* stencil_column_store */
   void* workspace;      /* device memory for STENCIL_IMPL_PLAIN temporaries */
   size_t workspace_bytes;
@@ -296,8 +298,8 @@ int stencil_coeff_field_adjoint(stencil_dtype dtype, const stencil_field* u, con
  * fused kernels only (impl PLAIN, or a PERIODIC boundary: STENCIL_E_UNSUPPORTED).  Items with an
  * empty domain are skipped (their outputs untouched), except that an
  * adjoint item with nk > 0 and an empty horizontal domain zeroes u_bar as
- * the single-field adjoint does.  The tile is opts->tile_i, else the tuning
- * table's entry for the batch's largest field. */
+ * the single-field adjoint does.  The forward's tile is opts->tile_i, else
+ * the tuning table's entry for the batch's largest field. */
 
 /* One field of a batch: forward step out = step(u, data, w) on `domain`. */
 typedef struct {
@@ -335,8 +337,9 @@ int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* i
                          size_t ws_bytes, const stencil_options* opts, hipStream_t stream);
 /* The adjoints of a batch: one persistent launch for the column adjoints
  * (work items: field, 64x4 column tile), one for the horizontal gathers
- * (work items: field, tile of the padded domain, block of levels).  ws as
- * for the forward, sized by stencil_batch_adjoint_workspace_bytes. */
+ * (work items: field, four 60x16 strips of the padded domain, block of
+ * levels).  ws as for the forward, sized by
+ * stencil_batch_adjoint_workspace_bytes; opts->tile_i is not used. */
 int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
                                  const stencil_batch_adjoint_item* items, void* ws,
                                  size_t ws_bytes, const stencil_options* opts,
@@ -358,7 +361,8 @@ int stencil_graph_launch(stencil_graph* graph, hipStream_t stream);
 int stencil_graph_destroy(stencil_graph* graph);
 
 /* ---------------------------------------------------------------- tuning */
-/* Times every tile candidate of `op` on a domain of this size (scratch
+/* Times every tile candidate of `op` (STENCIL_OP_STEP or STENCIL_OP_HDIFF;
+ * the other ops have no tile to choose: STENCIL_E_ARG) on a domain of this size (scratch
  * fields allocated and freed by the library for the duration of the call,
  * device synchronised) and records the fastest in the process-wide tuning
  * table under (dtype, op, size class).  *best_us receives its time. */

@@ -342,7 +342,7 @@ int run_hdiff_adjoint(const T* lam, int64_t l_sj, int64_t l_sk, const void* mask
   AdjArgs<T> A = adj_args<T>(nullptr, nullptr, const_cast<T*>(lam), l_sj, l_sk, ubar, dom, coeff,
                              0.0, (dom[0] == 0 || dom[1] == 0) ? nullptr : mask);
   apply_variant(A, r, coeff);
-  return hip_status(launch_hdiff_adjoint<T>(A, r.tile_i, s), "hdiff adjoint");
+  return hip_status(launch_hdiff_adjoint<T>(A, s), "hdiff adjoint");
 }
 
 template <typename T>

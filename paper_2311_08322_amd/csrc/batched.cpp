@@ -252,8 +252,7 @@ size_t adjoint_ws(stencil_dtype dt, int n, const stencil_batch_adjoint_item* it)
 }
 
 template <typename T>
-int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* ws, int tile_i, hipStream_t s) {
-  const int tile_j = kWG / tile_i;
+int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* ws, hipStream_t s) {
   const std::vector<int> vord = lpt_order(n, it, interior_work);
   const std::vector<int> hord = lpt_order(n, it, halo_work);
   if (hord.empty()) return ok();
@@ -300,7 +299,7 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
     vtotal += C.ntiles;
   }
 
-  // horizontal gathers: tiles over the padded domain, in blocks of levels
+  // horizontal gathers: groups of strips over the padded domain, in blocks of levels
   std::vector<AdjArgs<T>> hargs(mh);
   for (int e = 0; e < mh; ++e) {
     const int a = hord[e];
@@ -308,24 +307,25 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
     const bool empty = domain_empty(x.domain);
     AdjArgs<T> A = adj_args<T>(nullptr, nullptr, lam[a], lsj[a], lsk[a], const_cast<stencil_field*>(&x.u_bar),
                                x.domain, x.coeff, 0.0, empty ? nullptr : x.mask);
-    A.tiles_i = (A.ni + 4 + tile_i - 1) / tile_i;
-    A.ntiles = A.tiles_i * ((A.nj + 4 + tile_j - 1) / tile_j);
+    A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;
+    A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);  // strips
     hargs[e] = A;
   }
   // one level-block length for all fields: short enough for a few work items
-  // per resident workgroup, long enough to amortise each item's first level
+  // per resident workgroup
+  auto groups = [](const AdjArgs<T>& A) { return (int64_t)(A.ntiles + kStripsPerWG - 1) / kStripsPerWG; };
   int kper = 32;
   auto count = [&](int kp) {
     int64_t t = 0;
-    for (const auto& A : hargs) t += (int64_t)A.ntiles * ((A.nk + kp - 1) / kp);
+    for (const auto& A : hargs) t += groups(A) * ((A.nk + kp - 1) / kp);
     return t;
   };
-  while (kper > 4 && count(kper) < 8192) kper /= 2;
+  while (kper > 1 && count(kper) < 8192) kper /= 2;
   std::vector<int32_t> hitems(mh), hkper(mh);
   for (int e = 0; e < mh; ++e) {
     const int kp = std::min(kper, hargs[e].nk);
     hkper[e] = kp;
-    hitems[e] = hargs[e].ntiles * ((hargs[e].nk + kp - 1) / kp);
+    hitems[e] = (int32_t)(groups(hargs[e]) * ((hargs[e].nk + kp - 1) / kp));
   }
   const int64_t htotal = count(kper);
   if (vtotal > INT32_MAX / 2 || htotal > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
@@ -341,7 +341,7 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
   }
   BatchHeader* h = reinterpret_cast<BatchHeader*>(base + vbytes);
   const auto* ent = reinterpret_cast<const AdjArgs<T>*>(base + vbytes + table_head_bytes(mh));
-  return hip_status(launch_hadj_batched<T>(h, ent, (int)htotal, tile_i, s), "hdiff adjoint (batched)");
+  return hip_status(launch_hadj_batched<T>(h, ent, (int)htotal, s), "hdiff adjoint (batched)");
 }
 
 }  // namespace
@@ -386,9 +386,8 @@ int stencil_step_adjoint_batched(stencil_dtype dtype, int n, const stencil_batch
   TRY(check_workspace(ws, ws_bytes, need, sp));
   if (need == 0) return ok();
   TRY(check_device());
-  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP_ADJOINT, n, items);
-  return dtype == STENCIL_F64 ? run_step_adjoint_batched<double>(n, items, ws, ti, stream)
-                              : run_step_adjoint_batched<float>(n, items, ws, ti, stream);
+  return dtype == STENCIL_F64 ? run_step_adjoint_batched<double>(n, items, ws, stream)
+                              : run_step_adjoint_batched<float>(n, items, ws, stream);
 }
 
 }  // extern "C"

@@ -10,6 +10,10 @@ namespace gt4mi {
 constexpr int kHalo = 2;
 constexpr int kNumXcd = 8;        // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kWG = 256;          // threads per workgroup of every tile kernel
+// the hdiff adjoint's strips: 64 lanes in i (60 outputs), kStripRows rows in j
+constexpr int kStripOut = 60;
+constexpr int kStripRows = 16;
+constexpr int kStripsPerWG = kWG / 64;  // one strip per wave
 
 // ------------------------------------------------------------------ mask
 // Packed limiter decisions of one domain (1 = flux kept), see stencil.h.

@@ -20,7 +20,7 @@
 #include <string.h>
 
 #include "common.hpp"
-#include "k_hadj.hpp"
+#include "k_hadj_strip.hpp"
 #include "launch.hpp"
 
 namespace gt4mi {
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kWG) k_vadv_adjoint_bwd_plain(AdjArgs<T> A, co
 }
 
 // ---------------------------------------------------------------- horizontal
-// (the gather kernel is in k_hadj.hpp)
+// (the gather kernel is in k_hadj_strip.hpp)
 
 // ---------------------------------------------------------------- launchers
 template <typename T>
@@ -113,34 +113,23 @@ hipError_t launch_vadv_adjoint(AdjArgs<T> A, int impl_plain, T* ws_y, T* ws_c, h
   }
 }
 
+// strips of 60 x kStripRows outputs over the padded domain, four per
+// workgroup, one level per grid row
 template <typename T>
-hipError_t launch_hdiff_adjoint(AdjArgs<T> A, int tile_i, hipStream_t s) {
-  const int tile_j = kWG / tile_i;
-  A.tiles_i = (A.ni + 4 + tile_i - 1) / tile_i;
-  A.ntiles = A.tiles_i * ((A.nj + 4 + tile_j - 1) / tile_j);
-  int kper = A.nk;
-  while (kper > 4 && (int64_t)A.ntiles * ((A.nk + kper - 1) / kper) < 4096) kper = (kper + 1) / 2;
-  dim3 grid(A.ntiles, (A.nk + kper - 1) / kper), block(kWG);
-  const bool var = A.kappa != nullptr && A.lam != nullptr;  // per-point coefficient
-#define GT4MI_HADJ_LAUNCH(TI, TJ)                                                        \
-  if (var)                                                                               \
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, TI, TJ, true>), grid, block, 0, s, A, kper);  \
-  else                                                                                   \
-    hipLaunchKernelGGL((k_hdiff_adjoint<T, TI, TJ, false>), grid, block, 0, s, A, kper);
-  if (tile_i == 64) {
-    GT4MI_HADJ_LAUNCH(64, 4)
-  } else if (tile_i == 32) {
-    GT4MI_HADJ_LAUNCH(32, 8)
-  } else {
-    GT4MI_HADJ_LAUNCH(16, 16)
-  }
-#undef GT4MI_HADJ_LAUNCH
+hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s) {
+  A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;
+  A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);
+  const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
+  if (A.kappa != nullptr && A.lam != nullptr)  // per-point coefficient
+    hipLaunchKernelGGL((k_hdiff_adjoint_strip<T, true>), grid, block, 0, s, A);
+  else
+    hipLaunchKernelGGL((k_hdiff_adjoint_strip<T, false>), grid, block, 0, s, A);
   return hipGetLastError();
 }
 
 template hipError_t launch_vadv_adjoint<float>(AdjArgs<float>, int, float*, float*, hipStream_t);
 template hipError_t launch_vadv_adjoint<double>(AdjArgs<double>, int, double*, double*, hipStream_t);
-template hipError_t launch_hdiff_adjoint<float>(AdjArgs<float>, int, hipStream_t);
-template hipError_t launch_hdiff_adjoint<double>(AdjArgs<double>, int, hipStream_t);
+template hipError_t launch_hdiff_adjoint<float>(AdjArgs<float>, hipStream_t);
+template hipError_t launch_hdiff_adjoint<double>(AdjArgs<double>, hipStream_t);
 
 }  // namespace gt4mi

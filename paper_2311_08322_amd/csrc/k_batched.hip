@@ -6,14 +6,14 @@
 // items, then one argument block per field) with small copy kernels, so the
 // whole call is stream-ordered device work that a HIP graph can capture.
 // Every workgroup of the persistent launch then pulls work items (field,
-// tile[, level block]) from an atomic queue in the header until the queue is
-// exhausted.  A work item runs the same tile body as the single-field
-// kernel, picked by the field's column length.
+// tile or strips[, level block]) from an atomic queue in the header until
+// the queue is exhausted.  A work item runs the same body as the
+// single-field kernel (the step's tile picked by the field's column length).
 #include <string.h>
 
 #include "common.hpp"
 #include "k_colsplit.hpp"
-#include "k_hadj.hpp"
+#include "k_hadj_strip.hpp"
 #include "k_split.hpp"
 #include "launch.hpp"
 #include "persist.hpp"
@@ -135,10 +135,10 @@ __global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const 
   }
 }
 
-// Horizontal adjoint: work items (field, tile, level block).
-template <typename T, int TI, int TJ>
-__global__ void __launch_bounds__(TI* TJ) k_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent) {
-  __shared__ HadjSmem<T, TI, TJ> sm;
+// Horizontal adjoint: work items (field, group of kStripsPerWG strips, level
+// block); each wave walks its strip of the group through the block's levels.
+template <typename T>
+__global__ void __launch_bounds__(kWG) k_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent) {
   __shared__ int slot;
   for (;;) {
     const int w = next_work(h, &slot);
@@ -146,10 +146,14 @@ __global__ void __launch_bounds__(TI* TJ) k_hadj_batched(BatchHeader* h, const A
     const int e = find_entry(h, w);
     const AdjArgs<T> A = uniform_ld(ent + e);
     const int local = w - uniform_ld(h->prefix() + e);
-    const int tile = local % A.ntiles, kb = local / A.ntiles;
+    const int groups = (A.ntiles + kStripsPerWG - 1) / kStripsPerWG;
+    const int g = local % groups, kb = local / groups;
     const int kper = uniform_ld(h->kper() + e);
-    hdiff_adjoint_tile<T, TI, TJ>(A, tile, kb * kper, min(kb * kper + kper, A.nk), sm);
-    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(g * kStripsPerWG + (int)(threadIdx.x >> 6));
+    if (t < A.ntiles) {
+      const int kend = min(kb * kper + kper, A.nk);
+      for (int k = kb * kper; k < kend; ++k) hdiff_adjoint_strip<T, kStripRows, kStripPD, false>(A, t, k);
+    }
   }
 }
 
@@ -175,21 +179,16 @@ hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total
 }
 
 template <typename T>
-hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, int tile_i, hipStream_t s) {
-  auto go = [&](auto kernel) {
-    const int grid = persistent_grid(kernel, kWG, total);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, h, ent);
-    return hipGetLastError();
-  };
-  if (tile_i == 64) return go(k_hadj_batched<T, 64, 4>);
-  if (tile_i == 32) return go(k_hadj_batched<T, 32, 8>);
-  return go(k_hadj_batched<T, 16, 16>);
+hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, hipStream_t s) {
+  const int grid = persistent_grid(k_hadj_batched<T>, kWG, total);
+  hipLaunchKernelGGL(k_hadj_batched<T>, dim3(grid), dim3(kWG), 0, s, h, ent);
+  return hipGetLastError();
 }
 
 // one object per element type (-DGT4MI_T=float|double); the float one also
 // holds the table upload (-DGT4MI_UPLOAD)
 template hipError_t launch_step_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool, hipStream_t);
 template hipError_t launch_vadj_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, hipStream_t);
-template hipError_t launch_hadj_batched<GT4MI_T>(BatchHeader*, const AdjArgs<GT4MI_T>*, int, int, hipStream_t);
+template hipError_t launch_hadj_batched<GT4MI_T>(BatchHeader*, const AdjArgs<GT4MI_T>*, int, hipStream_t);
 
 }  // namespace gt4mi

@@ -1,0 +1,174 @@
+// k_hadj_strip.hpp -- the horizontal diffusion's adjoint (transposed gather).
+//
+// With the forward limiter decisions held fixed:
+//   gx(q)    = Mx(q) * (-coeff) * (mu(q) - mu(q + e_i))
+//   gy(q)    = My(q) * (-coeff) * (mu(q) - mu(q + e_j))
+//   lbar(q)  = gx(q - e_i) - gx(q) + gy(q - e_j) - gy(q)
+//   ubar(p)  = [p in I] lambda(p) + 4 lbar(p) - lbar(p +- e_i) - lbar(p +- e_j)
+// with mu = lambda (or kappa * lambda for a per-point coefficient), zero
+// outside the interior, and fluxes outside their definition sets zero.
+//
+// One wavefront owns a strip of 64 consecutive i (lane = i) and walks TJ
+// output rows in j at one level.  Neighbours in i come from the lanes next
+// door through DPP wave shifts (one register move per 32 bits); neighbours
+// in j are the rows before, held in registers as the walk advances.  No
+// LDS and no barriers: every wave runs on its own.  Each shift costs the
+// strip one lane at its edges, so of the 64 lanes the 60 in the middle
+// (lanes 2..61) write ubar; strips overlap by 4 columns.  A row of fluxes
+// needs the row after it, so the walk reads rows j0-2 .. j0+TJ+1 for the
+// outputs j0 .. j0+TJ-1, PD rows ahead of their use.  Strips cover the
+// padded domain [-2, ni+2) x [-2, nj+2); points outside the interior read
+// lambda = 0 and flux points outside their definition sets read mask 0.
+#pragma once
+
+#include "common.hpp"
+
+namespace gt4mi {
+
+constexpr int kStripPD = 4;  // rows in flight ahead of their use (PD)
+
+// DPP wave shifts of GFX9: lane l reads lane l+1 (shl) or lane l-1 (shr);
+// the lane past the wave's end reads 0.
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ uint32_t buf_ld_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+__device__ __forceinline__ uint32_t buf_ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+// The strip `t` (of A.tiles_i strips in i times the row blocks in j) at level k.
+template <typename T, int TJ, int PD, bool VAR>
+__device__ __forceinline__ void hdiff_adjoint_strip(const AdjArgs<T>& A, int t, int k) {
+  static_assert((TJ + 4) % PD == 0, "the row walk is unrolled by the prefetch depth");
+  constexpr uint32_t S = sizeof(T);
+  const int lane = threadIdx.x & 63;
+  const int si = t % A.tiles_i, sj = t / A.tiles_i;
+  const int ni = A.ni, nj = A.nj;
+  const int i = -4 + kStripOut * si + lane;  // lane 2 is the strip's first output column
+  const int j0 = -2 + TJ * sj;              // first output row
+  const bool iI = i >= 0 && i < ni;
+  const bool has_mask = A.mask != nullptr;
+  const bool outc = lane >= 2 && lane < 2 + kStripOut && i < ni + 2;
+  const T ncoeff = -A.coeff;
+
+  // Every access goes through a descriptor of one row (uniform: its base
+  // and a window of the row's width, 0 for a row outside the field) and a
+  // lane offset fixed for the whole walk; the window's range check drops
+  // the lanes past the row's end.
+  const char* lbase = reinterpret_cast<const char*>(A.lam) + (int64_t)k * A.l_sk * S;
+  [[maybe_unused]] const char* kbase = reinterpret_cast<const char*>(VAR ? A.kappa : A.lam) + (int64_t)k * A.c_sk * S;
+  const char* bbase = reinterpret_cast<const char*>(A.ubar) + ((int64_t)k * A.b_sk - 2 - 2 * A.b_sj) * S;
+  const char* mbase = reinterpret_cast<const char*>(A.mask);
+  const int64_t W = A.ml.words, plane_xy = (int64_t)nj * W * 8;
+  const char* xbase = mbase + A.ml.x_off + (int64_t)k * plane_xy;
+  const char* ybase = mbase + A.ml.y_off + (int64_t)k * plane_xy;
+  const auto row_rsrc = [&](const char* base, int64_t row_bytes, int r, int rows, uint32_t width) {
+    const bool in = r >= 0 && r < rows;
+    return make_rsrc(base + (in ? (int64_t)r * row_bytes : 0), in ? width : 0u);
+  };
+  const uint32_t l_off = i >= 0 ? (uint32_t)i * S : kOffNone;  // lambda, kappa (window: ni)
+  // the 32-bit half of the row's mask word that holds bit i
+  const uint32_t m_off = (iI && has_mask) ? (uint32_t)((i >> 6) * 8 + ((i >> 5) & 1) * 4) : kOffNone;
+  const int mbit = i & 31;
+  const uint32_t b_off = outc ? (uint32_t)(i + 2) * S : kOffNone;  // ubar (window: ni + 4)
+  const bool edge_i = si == 0;  // the strip holds i = -1, the x fluxes' extra column
+  const auto rex = make_rsrc(mbase + A.ml.ex_off + (int64_t)k * nj, has_mask ? (uint32_t)nj : 0u);
+  const auto rey = make_rsrc(mbase + A.ml.ey_off + (int64_t)k * ni, has_mask ? (uint32_t)ni : 0u);
+
+  // the edge fluxes' masks, read once per strip: Mx(-1, r) for the rows of
+  // the walk (lane l holds row r0 + l + 64 e; read back with readlane), and
+  // My(i, -1) for the strip's columns
+  const int r0 = j0 - 2;
+  constexpr int NR = TJ + 4, NEX = (NR + 63) / 64;
+  uint32_t exv[NEX];
+#pragma unroll
+  for (int e = 0; e < NEX; ++e) {
+    const int r = r0 + lane + 64 * e;
+    exv[e] = edge_i ? buf_ld_u8(rex, (r >= 0 && r < nj) ? (uint32_t)r : kOffNone) : 0u;
+  }
+  const bool edge_j = r0 <= -1;
+  const uint32_t eyv = edge_j ? buf_ld_u8(rey, iI ? (uint32_t)i : kOffNone) : 0u;
+
+  // the ring of rows in flight: raw loads, consumed PD rows later
+  T pl[PD];
+  [[maybe_unused]] T pk[VAR ? PD : 1];
+  uint32_t pmx[PD], pmy[PD];
+  auto issue = [&](int r, int s) {
+    pl[s] = buf_ld(row_rsrc(lbase, A.l_sj * S, r, nj, (uint32_t)ni * S), l_off, T());
+    if constexpr (VAR) pk[s] = buf_ld(row_rsrc(kbase, A.c_sj * S, r, nj, (uint32_t)ni * S), l_off, T());
+    pmx[s] = buf_ld_u32(row_rsrc(xbase, W * 8, r, nj, (uint32_t)(W * 8)), m_off);
+    pmy[s] = buf_ld_u32(row_rsrc(ybase, W * 8, r, nj, (uint32_t)(W * 8)), m_off);
+  };
+
+  // the walk's state: row r-1 (mu, lambda, gx, the My bit), r-2 (lambda,
+  // gy, lbar) and r-3 (lbar)
+  T mu1 = T(0), lam1 = T(0), lam2 = T(0), gx1 = T(0), gy2 = T(0), lb2 = T(0), lb3 = T(0);
+  bool my1 = false;
+  // row n of the walk (r = r0 + n) from ring slot s; refill the slot with row n + PD
+  auto step = [&](int n, int s, bool refill) {
+    const int r = r0 + n;
+    T lam = pl[s];
+    // a copy of its own: the slot's register is free for the refill while
+    // lambda lives on in the walk's state
+    asm volatile("" : "+v"(lam));
+    T mu = lam;
+    if constexpr (VAR) mu = pk[s] * lam;
+    const uint32_t ex = (uint32_t)__builtin_amdgcn_readlane((int)exv[NEX == 1 ? 0 : n / 64], n % 64);
+    const bool mx = ((pmx[s] >> mbit) & 1) | (i == -1 && ex != 0u);  // Mx(r)
+    const bool my = ((pmy[s] >> mbit) & 1) | (r == -1 && eyv != 0u);  // My(r)
+    if (refill) issue(r + PD, s);
+    // the shifts run with every lane active (a disabled lane would read as 0)
+    const T mu_e = lane_shift<kDppWaveShl1>(mu), gx1_w = lane_shift<kDppWaveShr1>(gx1);
+    const T lb2_e = lane_shift<kDppWaveShl1>(lb2), lb2_w = lane_shift<kDppWaveShr1>(lb2);
+    const T gx = mx ? ncoeff * (mu - mu_e) : T(0);   // gx(r)
+    const T gy1 = my1 ? ncoeff * (mu1 - mu) : T(0);  // gy(r-1)
+    const T lb1 = (gx1_w - gx1) + (gy2 - gy1);       // lbar(r-1)
+    const int q = r - 2;                             // ubar(r-2)
+    const T v = lam2 + T(4) * lb2 - lb2_e - lb2_w - lb1 - lb3;
+    if (q >= j0) buf_st(row_rsrc(bbase, A.b_sj * S, q + 2, nj + 4, (uint32_t)(ni + 4) * S), b_off, v);
+    lb3 = lb2;
+    lb2 = lb1;
+    gy2 = gy1;
+    gx1 = gx;
+    mu1 = mu;
+    my1 = my;
+    lam2 = lam1;
+    lam1 = lam;
+  };
+
+#pragma unroll
+  for (int s = 0; s < PD; ++s) issue(r0 + s, s);
+  int n = 0;
+  for (; n < NR - PD; n += PD) {
+#pragma unroll
+    for (int s = 0; s < PD; ++s) step(n + s, s, true);
+  }
+#pragma unroll
+  for (int s = 0; s < PD; ++s) step(n + s, s, false);
+}
+
+// One strip per wave, at one level per grid row.
+template <typename T, bool VAR>
+__global__ void __launch_bounds__(kWG) k_hdiff_adjoint_strip(AdjArgs<T> A) {
+  // the wave's strip (uniform: the conditions on it stay scalar branches)
+  const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
+                                               (int)(threadIdx.x >> 6));
+  if (t >= A.ntiles) return;  // whole waves only: no barrier follows
+  hdiff_adjoint_strip<T, kStripRows, kStripPD, VAR>(A, t, blockIdx.y);
+}
+
+}  // namespace gt4mi

@@ -60,7 +60,7 @@ hipError_t launch_vadv_adjoint(AdjArgs<T> A, int impl_plain, T* ws_y, T* ws_c, h
 template <typename T, int COL>
 hipError_t launch_vadj_classes(const AdjArgs<T>& A, hipStream_t s);
 template <typename T>
-hipError_t launch_hdiff_adjoint(AdjArgs<T> A, int tile_i, hipStream_t s);
+hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s);
 
 // persistent batched launches (k_batched.hip).  The work list sits in device
 // memory: a BatchHeader, then prefix[n + 1] (first work item of each field)
@@ -84,7 +84,7 @@ hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total
 template <typename T>
 hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s);
 template <typename T>
-hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, int tile_i, hipStream_t s);
+hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, hipStream_t s);
 
 // parameter gradients of a step (k_param.hip)
 template <typename T>

@@ -100,8 +100,9 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   if (check_dtype(dtype)) return STENCIL_E_DTYPE;
   if (int rc = check_domain(domain)) return rc;
   if (domain_empty(domain)) return fail(STENCIL_E_SHAPE, "cannot tune an empty domain");
-  if (op != STENCIL_OP_STEP && op != STENCIL_OP_HDIFF && op != STENCIL_OP_HDIFF_ADJOINT &&
-      op != STENCIL_OP_STEP_ADJOINT)
+  // the adjoints' gather walks fixed strips and their column solve has no
+  // tile: only the forward kernels have a tile to choose
+  if (op != STENCIL_OP_STEP && op != STENCIL_OP_HDIFF)
     return fail(STENCIL_E_ARG, "op %d has no tile choice to tune", op);
   if (reps <= 0) reps = 5;
   if (int rc = check_device()) return rc;
@@ -116,10 +117,9 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   void* pd = sc.alloc(inter);
   void* pw = sc.alloc(stag);
   void* pm = sc.alloc(stencil_mask_bytes(domain));
-  void* pl = sc.alloc(inter);
-  const size_t wsb = stencil_workspace_bytes(STENCIL_OP_STEP_ADJOINT, dtype, domain, nullptr);
+  const size_t wsb = stencil_workspace_bytes(op, dtype, domain, nullptr);
   void* pws = wsb ? sc.alloc(wsb) : nullptr;
-  if (!pu || !po || !pd || !pw || !pm || !pl || (wsb && !pws))
+  if (!pu || !po || !pd || !pw || !pm || (wsb && !pws))
     return fail(STENCIL_E_HIP, "autotune: scratch allocation failed");
   hipStream_t s;
   if (hipStreamCreate(&s) != hipSuccess) return fail(STENCIL_E_HIP, "autotune: stream");
@@ -132,16 +132,9 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   fill(po, padded, 0.0, 1.0, 2u);
   fill(pd, inter, -0.1, 0.1, 3u);
   fill(pw, stag, -1.0, 1.0, 4u);
-  fill(pl, inter, -1.0, 1.0, 5u);
   stencil_field u = make_field(pu, ni, nj, nk, 2, 0), out = make_field(po, ni, nj, nk, 2, 0);
   stencil_field data = make_field(pd, ni, nj, nk, 0, 0), w = make_field(pw, ni, nj, nk, 0, 1);
-  stencil_field xb = make_field(pl, ni, nj, nk, 0, 0);
-  // the mask must hold a forward's decisions before an adjoint reads it
-  int rc = stencil_step(dtype, &u, &data, &w, &out, domain, 0.025, 0.5, pm, nullptr, s);
-  if (rc) {
-    (void)hipStreamDestroy(s);
-    return rc;
-  }
+  int rc = 0;
   struct Cand {
     int ti, tj, col;
   };
@@ -152,7 +145,7 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
       if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS});
       if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF});
     } else {
-      cands.push_back({t, 256 / t, STENCIL_COLUMN_AUTO});
+      cands.push_back({t, 256 / t, STENCIL_COLUMN_AUTO});  // hdiff
     }
   }
   hipEvent_t e0, e1;
@@ -172,9 +165,7 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
     auto run = [&]() -> int {
       switch (op) {
         case STENCIL_OP_STEP: return stencil_step(dtype, &u, &data, &w, &out, domain, 0.025, 0.5, pm, &o, s);
-        case STENCIL_OP_HDIFF: return stencil_hdiff(dtype, &u, &out, domain, 0.025, pm, &o, s);
-        case STENCIL_OP_HDIFF_ADJOINT: return stencil_hdiff_adjoint(dtype, &xb, pm, &out, domain, 0.025, &o, s);
-        default: return stencil_step_adjoint(dtype, &xb, &w, pm, &out, nullptr, domain, 0.025, 0.5, &o, s);
+        default: return stencil_hdiff(dtype, &u, &out, domain, 0.025, pm, &o, s);
       }
     };
     rc = run();  // warm-up
