@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--only-step", action="store_true", help="time the fused forward step only")
     ap.add_argument("--with-frontend", action="store_true",
                     help="with --only-step: also time the step written in the stencil language")
+    ap.add_argument("--with-adjoint", action="store_true",
+                    help="with --only-step: also run the step adjoint a few times (counter collection)")
     ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only time a plain device copy of this many MiB (counter calibration)")
@@ -285,6 +287,16 @@ def main():
             o = api.Options(tile_i=tile, tile_j=256 // tile, column_store=api.COLUMN_SPLIT)
             for n in range(3):
                 api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
+        if args.with_adjoint:
+            # the step adjoint (column adjoint + gather) on the forward's mask
+            mask = fields.mask_tensor(dims, dev)
+            api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, mask=mask)
+            xb = fields.from_interior(inputs.cotangent(ni, nj, nk), torch.float64, dev)
+            ub = fields.alloc(ni, nj, nk, torch.float64, dev, fill=0.0)
+            db = fields.alloc(ni, nj, nk, torch.float64, dev, halo=0, fill=0.0)
+            for n in range(3):
+                api.stencil_step_adjoint(xb, w, mask, ub, db, dims, inputs.COEFF, inputs.DT_DZ)
+            del mask, xb, ub, db
         torch.cuda.synchronize()
         del u_a, u_b, data, w
     if not args.only_step:
