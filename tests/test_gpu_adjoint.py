@@ -212,3 +212,41 @@ def test_autograd_wiring():
     assert rel_err(host(x2), host(x)) <= 1e-14
     assert rel_err(host(u2.grad), host(u.grad)) <= 1e-13
     assert rel_err(host(d2.grad), host(data.grad)) <= 1e-13
+
+
+# The gather's strips hold 60 output columns (i from -2 + 60 s) and 16 output
+# rows (j from -2 + 16 t) of the padded domain: domains whose padded width or
+# height ends exactly on, or one past, a strip edge, plus the smallest ones.
+STRIP_EDGE_CASES = [(56, 12, 2), (57, 13, 3), (116, 28, 2), (117, 29, 2), (55, 11, 2), (1, 2, 3), (2, 1, 2),
+                    (176, 44, 1)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("field", [False, True], ids=["scalar", "kappa"])
+@pytest.mark.parametrize("dims", STRIP_EDGE_CASES, ids=lambda d: "x".join(map(str, d)))
+def test_hdiff_adjoint_strip_edges(dims, field, dtype):
+    ni, nj, nk = dims
+    print(f"hdiff adjoint strip edges {dims} field={field} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=204)
+    r = _ref(f, dtype)
+    u = fields.from_padded(f.u, dtype, DEV)
+    out = fields.alloc(ni, nj, nk, dtype, DEV, fill=0.0)
+    mask = fields.mask_tensor(dims, DEV)
+    api.stencil_hdiff(u, out, dims, inputs.COEFF, mask=mask)
+    lam = inputs.cotangent(ni, nj, nk)
+    kap = inputs.coeff_field(ni, nj, nk) if field else None
+    rr = (lambda a: round_f32(a)) if dtype == torch.float32 else (lambda a: a)
+    lb = fields.from_interior(lam, dtype, DEV)
+    ub = fields.alloc(ni, nj, nk, dtype, DEV, fill=9.0)
+    before = ub.tensor.clone()
+    o = api.Options(coeff_field=fields.from_interior(kap, dtype, DEV)) if field else None
+    api.stencil_hdiff_adjoint(lb, mask, ub, dims, inputs.COEFF, opts=o)
+    torch.cuda.synchronize()
+    mx, my = orc.hdiff_masks(r.u, decide_f32=(dtype == torch.float32))
+    ubr = orc.hdiff_adjoint(rr(lam), mx, my, c_scalar(inputs.COEFF, dtype), kappa=None if kap is None else rr(kap))
+    assert rel_err(host(fields.padded(ub, ni, nj, nk)), ubr) <= TOL[dtype]
+    # nothing outside the padded domain is written (row pitch, alignment offset)
+    oi, oj, ok = ub.origin
+    outside = torch.ones_like(before, dtype=torch.bool)
+    outside[ok:ok + nk, oj - 2:oj + nj + 2, oi - 2:oi + ni + 2] = False
+    assert torch.equal(ub.tensor[outside], before[outside])
