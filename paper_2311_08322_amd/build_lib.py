@@ -41,7 +41,8 @@ def _units():
                       [f"-DGT4MI_T={t}", "-DGT4MI_COLSPLIT", f"-DGT4MI_ADJ={adj}", *UNROLL]))
         for ti in (64, 32, 16):
             u.append(("k_step_inst.hip", f"split_{t}_{ti}",
-                      [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", *UNROLL]))
+                      [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT",
+                       *(["-DGT4MI_SPLIT_LONG"] if t == "double" else []), *UNROLL]))
             u.append(("k_step_inst.hip", f"splitvar_{t}_{ti}",
                       [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", "-DGT4MI_VAR", *UNROLL]))
         for col in cols:

@@ -10,6 +10,11 @@ namespace gt4mi {
 constexpr int kHalo = 2;
 constexpr int kNumXcd = 8;        // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kWG = 256;          // threads per workgroup of every tile kernel
+// the two-ended fused step in FP64: columns up to kSplitRegNkF64 levels in
+// 256-column tiles with e and f in VGPRs; longer ones (up to 144) in
+// kSplitLongNT-column tiles
+constexpr int kSplitRegNkF64 = 96;
+constexpr int kSplitLongNT = 128;
 // the hdiff adjoint's strips: 64 lanes in i (60 outputs), kStripRows rows in j
 constexpr int kStripOut = 60;
 constexpr int kStripRows = 16;

@@ -88,7 +88,7 @@ __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Forward step.  FP64 columns up to 80 levels keep both halves' factors in
+// Forward step.  FP64 columns up to 96 levels keep both halves' factors in
 // VGPRs, longer ones (up to 144) stage f in `out`; FP32 keeps all up to 144.
 template <typename T, int TI, int TJ, bool MASK>
 __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
@@ -103,6 +103,8 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     if constexpr (sizeof(T) == 8) {
       if (A.nk <= 80)
         step_split_tile<T, TI, TJ, 40, GT4MI_PD, MASK, 1>(A, tile, sm);
+      else if (A.nk <= kSplitRegNkF64)
+        step_split_tile<T, TI, TJ, 48, GT4MI_PD, MASK, 1>(A, tile, sm);
       else
         step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 2>(A, tile, sm);
     } else {

@@ -258,10 +258,12 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
 
 // One instantiation per half-column register class.  With the early exit a
 // class costs only its registers, so the classes are coarse.  FP64 keeps e
-// and f of both halves in VGPRs up to 80 levels; longer FP64 columns (up to
-// 144) keep e and stage f in the output.
-#define GT4MI_NKH_CLASSES(X) X(16) X(24) X(40) X(56) X(80)
-constexpr int kSplitRegNkF64 = 80;
+// and f of both halves in VGPRs up to 96 levels (class 48: 244-250 VGPRs, two
+// waves per SIMD).  Longer FP64 columns (up to 144) run in 128-column tiles
+// with e and f in VGPRs at one wave per SIMD (launch_split_long); where that
+// form is not instantiated (the generalised diffusion, the batched kernel)
+// they keep e and stage f in the output.
+#define GT4MI_NKH_CLASSES(X) X(16) X(24) X(40) X(48) X(56) X(80)
 constexpr int kSplitStagedNkhF64 = 72;
 
 template <typename T>
@@ -282,7 +284,7 @@ hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s) {
     return hipGetLastError();                                                                        \
   }
 #define GT4MI_SPLIT_CASE(N)                                                                  \
-  if constexpr (2 * N <= (sizeof(T) == 8 ? kSplitRegNkF64 : 160)) {                          \
+  if constexpr (2 * N <= (sizeof(T) == 8 ? kSplitRegNkF64 : 160) && (sizeof(T) == 8 || N != 48)) { \
     if (nkh <= N) GT4MI_SPLIT_LAUNCH(N, 1)                                                   \
   }
   GT4MI_NKH_CLASSES(GT4MI_SPLIT_CASE)
@@ -292,6 +294,22 @@ hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s) {
 #undef GT4MI_SPLIT_CASE
 #undef GT4MI_SPLIT_LAUNCH
   return hipErrorInvalidValue;
+}
+
+// FP64 columns of 97..144 levels: TI x (kSplitLongNT / TI) tiles of 256 lanes,
+// e and f of both halves in VGPRs (about 360; no spills).  A.tiles_i and
+// A.ntiles count tiles of that shape.
+template <typename T, int TI>
+hipError_t launch_split_long(const StepArgs<T>& A, hipStream_t s) {
+  static_assert(sizeof(T) == 8, "binary32 columns fit the 256-column classes");
+  constexpr int TJ = kSplitLongNT / TI;
+  const dim3 grid(A.ntiles), block(2 * TI * TJ);
+  if (A.nk - A.nk / 2 > kSplitStagedNkhF64) return hipErrorInvalidValue;
+  if (A.mask)
+    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD, true, 1, false>), grid, block, 0, s, A);
+  else
+    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD, false, 1, false>), grid, block, 0, s, A);
+  return hipGetLastError();
 }
 
 }  // namespace gt4mi

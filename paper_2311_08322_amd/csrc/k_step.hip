@@ -16,6 +16,16 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
   const bool var = A.kappa != nullptr || A.form != 0;  // the generalised diffusion: two-ended step only
   if (var || (col == 3 && A.nk <= split_step_limit(sizeof(T)))) {  // STENCIL_COLUMN_SPLIT
     if (A.nk > split_step_limit(sizeof(T))) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 8) {
+      if (!var && A.nk > kSplitRegNkF64) {  // 97..144 levels: 128-column tiles, all in VGPRs
+        const int tj = kSplitLongNT / tile_i;
+        A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+        A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
+        if (tile_i == 64) return launch_split_long<T, 64>(A, s);
+        if (tile_i == 32) return launch_split_long<T, 32>(A, s);
+        return launch_split_long<T, 16>(A, s);
+      }
+    }
     constexpr int NT = GT4MI_SPLIT_NT;
     const int tj = NT / tile_i;
     A.tiles_i = (A.ni + tile_i - 1) / tile_i;

@@ -21,6 +21,9 @@ hipError_t launch_vadv_classes(const StepArgs<T>& A, hipStream_t s);
 // VAR: the generalised diffusion (per-point coefficient, damping form)
 template <typename T, int TI, int TJ, bool VAR>
 hipError_t launch_split_classes(const StepArgs<T>& A, hipStream_t s);
+// FP64 columns of 97..144 levels in 128-column tiles (k_split.hpp)
+template <typename T, int TI>
+hipError_t launch_split_long(const StepArgs<T>& A, hipStream_t s);
 // two-ended column solve: ADJ = false, out = T^{-1}(u + data);
 // ADJ = true, out = T^{-T} u (u holds x_bar); nk <= 144 (FP64) / 160 (FP32)
 template <typename T, bool ADJ>

@@ -114,8 +114,10 @@ def test_vadv_full_size_residual():
 
 
 # ------------------------------------------------------------------ step
+# column lengths at the FP64 register classes' edges too: 88 and 96 (half
+# columns of 48 levels), 97 and 144 (the 128-column long form)
 STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (9, 5, 2), (30, 70, 79), (33, 17, 137),
-              (20, 20, 161)]
+              (20, 20, 161), (45, 21, 88), (37, 19, 96), (29, 23, 97), (21, 13, 144)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
