@@ -88,8 +88,10 @@ __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Forward step.  FP64 columns up to 96 levels keep both halves' factors in
-// VGPRs, longer ones (up to 144) stage f in `out`; FP32 keeps all up to 144.
+// Forward step.  FP64 columns up to 80 levels keep both halves' factors in
+// VGPRs, longer ones (up to 144) stage f in `out` (one kernel holds every
+// body, so its VGPR budget is the largest body's: the 48-level class of the
+// single-field step would make it spill); FP32 keeps all up to 144.
 template <typename T, int TI, int TJ, bool MASK>
 __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
   __shared__ SplitSmem<T, TI, TJ> sm;
@@ -103,8 +105,6 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     if constexpr (sizeof(T) == 8) {
       if (A.nk <= 80)
         step_split_tile<T, TI, TJ, 40, GT4MI_PD, MASK, 1>(A, tile, sm);
-      else if (A.nk <= kSplitRegNkF64)
-        step_split_tile<T, TI, TJ, 48, GT4MI_PD, MASK, 1>(A, tile, sm);
       else
         step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 2>(A, tile, sm);
     } else {

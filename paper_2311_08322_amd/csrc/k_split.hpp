@@ -261,8 +261,8 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
 // and f of both halves in VGPRs up to 96 levels (class 48: 244-250 VGPRs, two
 // waves per SIMD).  Longer FP64 columns (up to 144) run in 128-column tiles
 // with e and f in VGPRs at one wave per SIMD (launch_split_long); where that
-// form is not instantiated (the generalised diffusion, the batched kernel)
-// they keep e and stage f in the output.
+// form is not instantiated (the generalised diffusion) they keep e and
+// stage f in the output, as the batched kernel does beyond 80 levels.
 #define GT4MI_NKH_CLASSES(X) X(16) X(24) X(40) X(48) X(56) X(80)
 constexpr int kSplitStagedNkhF64 = 72;
 
