@@ -205,34 +205,62 @@ int32_t write_table(std::vector<uint8_t>& blob, size_t off, const std::vector<Ar
 }
 
 // ---------------------------------------------------------------- forward
+// FP64 fields whose columns exceed kBatchedShortNkF64 levels run in a launch
+// of their own (128-column tiles, e and f in VGPRs); the rest share one launch.
+bool long_fp64(stencil_dtype dt, const int64_t* d) { return dt == STENCIL_F64 && d[2] > kBatchedShortNkF64; }
+
+// Table sizes of the forward batch: [short group, long group].
+void forward_groups(stencil_dtype dt, int n, const stencil_batch_item* it, int m[2]) {
+  m[0] = m[1] = 0;
+  for (int a = 0; a < n; ++a)
+    if (interior_work(it[a].domain)) ++m[long_fp64(dt, it[a].domain) ? 1 : 0];
+}
+
 template <typename T>
 int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, hipStream_t s) {
-  const int tile_j = kWG / tile_i;
+  constexpr stencil_dtype dt = sizeof(T) == 8 ? STENCIL_F64 : STENCIL_F32;
   const std::vector<int> ord = lpt_order(n, it, interior_work);
   if (ord.empty()) return ok();
-  const int m = (int)ord.size();
-  std::vector<StepArgs<T>> args(m);
-  std::vector<int32_t> items(m);
-  bool any_mask = false;
-  int64_t total = 0;
-  for (int e = 0; e < m; ++e) {
-    const stencil_batch_item& x = it[ord[e]];
-    StepArgs<T> A = step_args<T>(&x.u, &x.data, &x.w, const_cast<stencil_field*>(&x.out), x.domain, x.coeff,
-                                 x.dt_dz, x.mask);
-    A.tiles_i = (A.ni + tile_i - 1) / tile_i;
-    A.ntiles = A.tiles_i * ((A.nj + tile_j - 1) / tile_j);
-    args[e] = A;
-    items[e] = A.ntiles;
-    total += A.ntiles;
-    any_mask |= x.mask != nullptr;
+  char* base = static_cast<char*>(ws);
+  int64_t off = 0;
+  // the long group first: its columns are the longest (longest work first)
+  for (int g = 1; g >= 0; --g) {
+    const int tile_j = (g ? kSplitLongNT : kWG) / tile_i;
+    std::vector<StepArgs<T>> args;
+    std::vector<int32_t> items;
+    bool any_mask = false;
+    int64_t total = 0;
+    for (int a : ord) {
+      const stencil_batch_item& x = it[a];
+      if (long_fp64(dt, x.domain) != (g == 1)) continue;
+      StepArgs<T> A = step_args<T>(&x.u, &x.data, &x.w, const_cast<stencil_field*>(&x.out), x.domain, x.coeff,
+                                   x.dt_dz, x.mask);
+      A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+      A.ntiles = A.tiles_i * ((A.nj + tile_j - 1) / tile_j);
+      args.push_back(A);
+      items.push_back(A.ntiles);
+      total += A.ntiles;
+      any_mask |= x.mask != nullptr;
+    }
+    const int m = (int)args.size();
+    if (m == 0) continue;
+    if (total > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch of %lld tiles is too large", (long long)total);
+    std::vector<uint8_t> blob((size_t)table_bytes(m, sizeof(StepArgs<T>)), 0);
+    write_table(blob, 0, args, items, {});
+    TRY(hip_status(launch_upload(base + off, blob.data(), blob.size(), s), "batched table upload"));
+    BatchHeader* h = reinterpret_cast<BatchHeader*>(base + off);
+    const auto* ent = reinterpret_cast<const StepArgs<T>*>(base + off + table_head_bytes(m));
+    if constexpr (sizeof(T) == 8) {  // only FP64 has a long group
+      if (g == 1) {
+        TRY(hip_status(launch_step_batched_long<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched, long)"));
+        off += (int64_t)blob.size();
+        continue;
+      }
+    }
+    TRY(hip_status(launch_step_batched<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched)"));
+    off += (int64_t)blob.size();
   }
-  if (total > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch of %lld tiles is too large", (long long)total);
-  std::vector<uint8_t> blob((size_t)table_bytes(m, sizeof(StepArgs<T>)), 0);
-  write_table(blob, 0, args, items, {});
-  TRY(hip_status(launch_upload(ws, blob.data(), blob.size(), s), "batched table upload"));
-  BatchHeader* h = static_cast<BatchHeader*>(ws);
-  const auto* ent = reinterpret_cast<const StepArgs<T>*>(static_cast<char*>(ws) + table_head_bytes(m));
-  return hip_status(launch_step_batched<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched)");
+  return ok();
 }
 
 // ---------------------------------------------------------------- adjoint
@@ -353,10 +381,12 @@ extern "C" {
 
 size_t stencil_batch_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_item* items) {
   if (check_dtype(dtype) || n <= 0 || n > kMaxBatch || !items) return 0;
-  int m = 0;
-  for (int a = 0; a < n; ++a)
-    if (!domain_empty(items[a].domain)) ++m;
-  return m ? (size_t)table_bytes(m, arg_bytes(dtype, false)) : 0;
+  int m[2];
+  forward_groups(dtype, n, items, m);
+  int64_t b = 0;
+  for (int g = 0; g < 2; ++g)
+    if (m[g]) b += table_bytes(m[g], arg_bytes(dtype, false));
+  return (size_t)b;
 }
 
 size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n, const stencil_batch_adjoint_item* items) {

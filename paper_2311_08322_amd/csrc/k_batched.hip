@@ -88,10 +88,10 @@ __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Forward step.  FP64 columns up to 80 levels keep both halves' factors in
-// VGPRs, longer ones (up to 144) stage f in `out` (one kernel holds every
-// body, so its VGPR budget is the largest body's: the 48-level class of the
-// single-field step would make it spill); FP32 keeps all up to 144.
+// Forward step.  FP64: the host sends columns up to kBatchedShortNkF64
+// levels here (both halves' factors in VGPRs, the 40-level class; the
+// 48-level class spills beside the persistent loop's own registers) and the
+// longer ones to k_step_batched_long; FP32 keeps all up to 144 here.
 template <typename T, int TI, int TJ, bool MASK>
 __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
   __shared__ SplitSmem<T, TI, TJ> sm;
@@ -103,16 +103,33 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     const StepArgs<T> A = uniform_ld(ent + e);
     const int tile = w - uniform_ld(h->prefix() + e);
     if constexpr (sizeof(T) == 8) {
-      if (A.nk <= 80)
-        step_split_tile<T, TI, TJ, 40, GT4MI_PD, MASK, 1>(A, tile, sm);
-      else
-        step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 2>(A, tile, sm);
+      step_split_tile<T, TI, TJ, kBatchedShortNkF64 / 2, GT4MI_PD, MASK, 1>(A, tile, sm);
     } else {
       step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 1>(A, tile, sm);
     }
     __syncthreads();  // the LDS is reused by the next item
   }
 }
+
+#ifdef GT4MI_BATCHED_LONG
+// FP64 columns of kBatchedShortNkF64+1 .. 144 levels: TI x (kSplitLongNT / TI)
+// tiles of 256 lanes with e and f in VGPRs, as the single-field long form.
+template <typename T, int TI, bool MASK>
+__global__ void __launch_bounds__(2 * kSplitLongNT) k_step_batched_long(BatchHeader* h, const StepArgs<T>* ent) {
+  constexpr int TJ = kSplitLongNT / TI;
+  __shared__ SplitSmem<T, TI, TJ> sm;
+  __shared__ int slot;
+  for (;;) {
+    const int w = next_work(h, &slot);
+    if (w < 0) break;
+    const int e = find_entry(h, w);
+    const StepArgs<T> A = uniform_ld(ent + e);
+    const int tile = w - uniform_ld(h->prefix() + e);
+    step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 1>(A, tile, sm);
+    __syncthreads();
+  }
+}
+#endif
 
 // Column adjoint lambda = T^{-T} x_bar (argument blocks in column form).
 template <typename T>
@@ -173,6 +190,21 @@ hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total
   return mask ? go(k_step_batched<T, 16, 16, true>) : go(k_step_batched<T, 16, 16, false>);
 }
 
+#ifdef GT4MI_BATCHED_LONG
+template <typename T>
+hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                                    hipStream_t s) {
+  auto go = [&](auto kernel) {
+    const int grid = persistent_grid(kernel, 2 * kSplitLongNT, total);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(2 * kSplitLongNT), 0, s, h, ent);
+    return hipGetLastError();
+  };
+  if (tile_i == 64) return mask ? go(k_step_batched_long<T, 64, true>) : go(k_step_batched_long<T, 64, false>);
+  if (tile_i == 32) return mask ? go(k_step_batched_long<T, 32, true>) : go(k_step_batched_long<T, 32, false>);
+  return mask ? go(k_step_batched_long<T, 16, true>) : go(k_step_batched_long<T, 16, false>);
+}
+#endif
+
 template <typename T>
 hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s) {
   const int grid = persistent_grid(k_vadj_batched<T>, 2 * kWG, total);
@@ -188,9 +220,14 @@ hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total,
 }
 
 // one object per element type (-DGT4MI_T=float|double); the float one also
-// holds the table upload (-DGT4MI_UPLOAD)
+// holds the table upload (-DGT4MI_UPLOAD), the double one the long-column
+// forward (-DGT4MI_BATCHED_LONG)
 template hipError_t launch_step_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool, hipStream_t);
 template hipError_t launch_vadj_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, hipStream_t);
 template hipError_t launch_hadj_batched<GT4MI_T>(BatchHeader*, const AdjArgs<GT4MI_T>*, int, hipStream_t);
+#ifdef GT4MI_BATCHED_LONG
+template hipError_t launch_step_batched_long<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool,
+                                                      hipStream_t);
+#endif
 
 }  // namespace gt4mi

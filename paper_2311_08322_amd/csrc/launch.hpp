@@ -84,6 +84,10 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 template <typename T>
 hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
                                hipStream_t s);
+// FP64 columns longer than kSplitRegNkF64 (tiles of kSplitLongNT columns)
+template <typename T>
+hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                                    hipStream_t s);
 template <typename T>
 hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s);
 template <typename T>
