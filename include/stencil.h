@@ -327,7 +327,9 @@ size_t stencil_batch_workspace_bytes(stencil_dtype dtype, int n, const stencil_b
 size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
                                              const stencil_batch_adjoint_item* items);
 
-/* All n steps in one persistent launch.  The call sorts the items longest
+/* All n steps in one persistent launch (FP64: two, one for the fields with
+ * columns of up to 80 levels, one for the longer ones, which run tiles of
+ * tile_i x (128 / tile_i) columns).  The call sorts the items longest
  * column first, writes the work list into `ws` with small copy kernels on
  * `stream` (stream-ordered, so the call can be captured into a graph), and
  * launches one kernel whose workgroups pull (field, tile) work items from a
