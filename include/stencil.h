@@ -332,7 +332,7 @@ size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
  * tile_i x (128 / tile_i) columns).  The call sorts the items longest
  * column first, writes the work list into `ws` with small copy kernels on
  * `stream` (stream-ordered, so the call can be captured into a graph), and
- * launches one kernel whose workgroups pull (field, tile) work items from a
+ * launches the kernel(s), whose workgroups pull (field, tile) work items from a
  * device counter in `ws` until none are left.  ws: device memory, 256-byte
  * aligned, at least stencil_batch_workspace_bytes(...) bytes, not
  * overlapping any field (STENCIL_E_WORKSPACE / STENCIL_E_ALIAS); two calls
