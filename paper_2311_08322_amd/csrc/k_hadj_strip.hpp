@@ -27,29 +27,6 @@ namespace gt4mi {
 
 constexpr int kStripPD = 4;  // rows in flight ahead of their use (PD)
 
-// DPP wave shifts of GFX9: lane l reads lane l+1 (shl) or lane l-1 (shr);
-// the lane past the wave's end reads 0.
-constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
-
-template <int CTRL>
-__device__ __forceinline__ float lane_shift(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double lane_shift(double v) {
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-__device__ __forceinline__ uint32_t buf_ld_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
-}
-__device__ __forceinline__ uint32_t buf_ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
-}
-
 // The strip `t` (of A.tiles_i strips in i times the row blocks in j) at level k.
 template <typename T, int TJ, int PD, bool VAR>
 __device__ __forceinline__ void hdiff_adjoint_strip(const AdjArgs<T>& A, int t, int k) {
