@@ -127,12 +127,13 @@ typedef enum {
 
 typedef struct {
   int32_t impl;         /* stencil_impl */
-  int32_t tile_i;       /* horizontal tile of the fused forward kernels (hdiff, */
-  int32_t tile_j;       /*   step, batched step); 0 = tuned; supported: 64x4,
-                           32x8, 16x16.  FP64 columns of 97..144 levels in the
-                           two-ended step run tile_i x (128 / tile_i) tiles.
-                           The adjoints' gather walks fixed strips and ignores
-                           it (the value is still validated). */
+  int32_t tile_i;       /* horizontal tile of the fused forward kernels (step, */
+  int32_t tile_j;       /*   batched step, hdiff of the generalised diffusion);
+                           0 = tuned; supported: 64x4, 32x8, 16x16.  FP64
+                           columns of 97..144 levels in the two-ended step run
+                           tile_i x (128 / tile_i) tiles.  The stated hdiff
+                           and the adjoints' gather walk fixed strips and
+                           ignore it (the value is still validated). */
   int32_t column_store; /* stencil_column_store */
   void* workspace;      /* device memory for STENCIL_IMPL_PLAIN temporaries */
   size_t workspace_bytes;
