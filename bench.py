@@ -222,18 +222,32 @@ def main():
         times.sort()
         return times[len(times) // 2]
 
-    def time_eager(fn, reps=20):
+    def time_eager(fn, reps=20, warm_s=0.03, windows=3):
+        """Per-call time of back-to-back eager calls: the median of `windows`
+        windows of `reps` calls, after calling fn for at least warm_s seconds
+        of device time (the first milliseconds after a change of workload
+        run measurably slower)."""
         s = torch.cuda.current_stream()
-        fn()
-        torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(s)
-        for _ in range(reps):
-            fn()
-        e1.record(s)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / reps
+        warm, calls = 0.0, 0
+        while warm < warm_s and calls < 2000:
+            e0.record(s)
+            for _ in range(4):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            warm += e0.elapsed_time(e1) / 1e3
+            calls += 4
+        ts = []
+        for _ in range(windows):
+            e0.record(s)
+            for _ in range(reps):
+                fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3 / reps)
+        return sorted(ts)[len(ts) // 2]
 
     # ------------------------------------------------------------ autotuning
     # the library's autotuner picks tile and column store for this size class
