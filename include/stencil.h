@@ -366,8 +366,9 @@ int stencil_graph_launch(stencil_graph* graph, hipStream_t stream);
 int stencil_graph_destroy(stencil_graph* graph);
 
 /* ---------------------------------------------------------------- tuning */
-/* Times every tile candidate of `op` (STENCIL_OP_STEP or STENCIL_OP_HDIFF;
- * the other ops have no tile to choose: STENCIL_E_ARG) on a domain of this size (scratch
+/* Times every tile candidate of `op` (STENCIL_OP_STEP, or STENCIL_OP_HDIFF,
+ * timed in the damping form: only the generalised diffusion's hdiff has a
+ * tile; the other ops have none to choose: STENCIL_E_ARG) on a domain of this size (scratch
  * fields allocated and freed by the library for the duration of the call,
  * device synchronised) and records the fastest in the process-wide tuning
  * table under (dtype, op, size class).  *best_us receives its time. */

@@ -264,3 +264,21 @@ def test_autograd_hdiff_coefficient_gradient(field):
         g = orc.coeff_grad(f.u, ob, mx, my, damping=True)
         scale = float(np.sum(np.abs(orc.coeff_field_grad(f.u, ob, mx, my, damping=True))))
         assert abs(float(c.grad.item()) - g) <= 1e-12 * scale
+
+
+def test_autotune_hdiff_damping():
+    """The tuner times hdiff's tile candidates in the damping form (the only
+    hdiff with a tile); the tuned tile then serves that form's calls."""
+    dims = (67, 45, 7)
+    ni, nj, nk = dims
+    best = api.stencil_autotune(torch.float64, api.OP_HDIFF, dims, reps=2)
+    assert best > 0
+    ti, tj, _ = api.stencil_tuning_lookup(torch.float64, api.OP_HDIFF, dims)
+    assert (ti, tj) in ((64, 4), (32, 8), (16, 16))
+    f = inputs.fields_sized(ni, nj, nk, seed=601)
+    u = fields.from_padded(f.u, torch.float64, DEV)
+    out = fields.alloc(ni, nj, nk, torch.float64, DEV, fill=0.0)
+    api.stencil_hdiff(u, out, dims, inputs.COEFF, opts=api.Options(hdiff_form=api.HDIFF_DAMPING))
+    torch.cuda.synchronize()
+    want, _, _ = orc.hdiff(f.u, inputs.COEFF, damping=True)
+    assert rel_err(host(fields.interior(out, ni, nj, nk)), want[:, 2:-2, 2:-2]) <= TOL[torch.float64]
