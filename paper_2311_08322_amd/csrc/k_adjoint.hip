@@ -117,10 +117,22 @@ hipError_t launch_vadv_adjoint(AdjArgs<T> A, int impl_plain, T* ws_y, T* ws_c, h
 // workgroup, one level per grid row
 template <typename T>
 hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s) {
+  const bool var = A.kappa != nullptr && A.lam != nullptr;  // per-point coefficient
+  if constexpr (sizeof(T) == 4) {
+    // binary32: two columns per lane, strips of 124 x kStripRows outputs
+    A.tiles_i = (A.ni + 4 + kStripOut2 - 1) / kStripOut2;
+    A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);
+    const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
+    if (var)
+      hipLaunchKernelGGL(k_hdiff_adjoint_strip2<true>, grid, block, 0, s, A);
+    else
+      hipLaunchKernelGGL(k_hdiff_adjoint_strip2<false>, grid, block, 0, s, A);
+    return hipGetLastError();
+  }
   A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;
   A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);
   const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
-  if (A.kappa != nullptr && A.lam != nullptr)  // per-point coefficient
+  if (var)
     hipLaunchKernelGGL((k_hdiff_adjoint_strip<T, true>), grid, block, 0, s, A);
   else
     hipLaunchKernelGGL((k_hdiff_adjoint_strip<T, false>), grid, block, 0, s, A);

@@ -214,11 +214,12 @@ def test_autograd_wiring():
     assert rel_err(host(d2.grad), host(data.grad)) <= 1e-13
 
 
-# The gather's strips hold 60 output columns (i from -2 + 60 s) and 16 output
-# rows (j from -2 + 16 t) of the padded domain: domains whose padded width or
-# height ends exactly on, or one past, a strip edge, plus the smallest ones.
+# The gather's strips hold 60 output columns in FP64 and 124 in FP32 (two
+# columns per lane), from i = -2, and 16 output rows from j = -2, of the
+# padded domain: domains whose padded width or height ends exactly on, or one
+# past, a strip edge of either width, plus the smallest ones.
 STRIP_EDGE_CASES = [(56, 12, 2), (57, 13, 3), (116, 28, 2), (117, 29, 2), (55, 11, 2), (1, 2, 3), (2, 1, 2),
-                    (176, 44, 1)]
+                    (176, 44, 1), (120, 12, 2), (121, 13, 2), (244, 5, 2), (245, 6, 2)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
