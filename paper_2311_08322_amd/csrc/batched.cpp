@@ -335,7 +335,8 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
     const bool empty = domain_empty(x.domain);
     AdjArgs<T> A = adj_args<T>(nullptr, nullptr, lam[a], lsj[a], lsk[a], const_cast<stencil_field*>(&x.u_bar),
                                x.domain, x.coeff, 0.0, empty ? nullptr : x.mask);
-    A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;
+    const int out_i = sizeof(T) == 4 ? kStripOut2 : kStripOut;  // FP32: two columns per lane
+    A.tiles_i = (A.ni + 4 + out_i - 1) / out_i;
     A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);  // strips
     hargs[e] = A;
   }

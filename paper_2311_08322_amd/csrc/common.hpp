@@ -20,6 +20,7 @@ constexpr int kSplitLongNT = 128;
 constexpr int kBatchedShortNkF64 = 80;
 // the hdiff adjoint's strips: 64 lanes in i (60 outputs), kStripRows rows in j
 constexpr int kStripOut = 60;
+constexpr int kStripOut2 = 124;  // FP32: two columns per lane, 124 outputs
 constexpr int kStripRows = 16;
 constexpr int kStripsPerWG = kWG / 64;  // one strip per wave
 

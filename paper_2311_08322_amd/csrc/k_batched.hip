@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const 
 }
 
 // Horizontal adjoint: work items (field, group of kStripsPerWG strips, level
-// block); each wave walks its strip of the group through the block's levels.
+// block); each wave walks its strip of the group through the block's levels
+// (FP32 strips hold two columns per lane, as in the single-field gather).
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent) {
   __shared__ int slot;
@@ -171,7 +172,12 @@ __global__ void __launch_bounds__(kWG) k_hadj_batched(BatchHeader* h, const AdjA
     const int t = __builtin_amdgcn_readfirstlane(g * kStripsPerWG + (int)(threadIdx.x >> 6));
     if (t < A.ntiles) {
       const int kend = min(kb * kper + kper, A.nk);
-      for (int k = kb * kper; k < kend; ++k) hdiff_adjoint_strip<T, kStripRows, kStripPD, false>(A, t, k);
+      for (int k = kb * kper; k < kend; ++k) {
+        if constexpr (sizeof(T) == 4)
+          hdiff_adjoint_strip2<kStripRows, kStripPD, false>(A, t, k);  // two columns per lane
+        else
+          hdiff_adjoint_strip<T, kStripRows, kStripPD, false>(A, t, k);
+      }
     }
   }
 }

@@ -144,7 +144,6 @@ __device__ __forceinline__ void hdiff_adjoint_strip(const AdjArgs<T>& A, int t, 
 // row needs half the shifts, and both columns' limiter bits sit in one 32-bit
 // word of each mask plane.  Same values as hdiff_adjoint_strip, in the same
 // order of operations.
-constexpr int kStripOut2 = 124;
 
 template <int TJ, int PD, bool VAR>
 __device__ __forceinline__ void hdiff_adjoint_strip2(const AdjArgs<float>& A, int t, int k) {
