@@ -12,8 +12,16 @@ hipError_t launch_hdiff_fused(StepArgs<T> A, int tile_i, hipStream_t s) {
   // the walk addresses the mask through one 32-bit window
   const bool small_mask = A.mask == nullptr || A.ml.total <= (int64_t)kOffNone - 16;
   if (!var && small_mask) {
-    // the row walk: strips of 56 x kHStripRows outputs, four per workgroup,
-    // one level per grid row (the tile option does not apply)
+    // the row walk: strips of 56 x kHStripRows outputs (FP32: 120, two
+    // columns per lane), four per workgroup, one level per grid row (the tile
+    // option does not apply)
+    if constexpr (sizeof(T) == 4) {
+      A.tiles_i = (A.ni + kHStripOut2 - 1) / kHStripOut2;
+      A.ntiles = A.tiles_i * ((A.nj + kHStripRows - 1) / kHStripRows);
+      const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
+      hipLaunchKernelGGL(k_hdiff_strip2, grid, block, 0, s, A);
+      return hipGetLastError();
+    }
     A.tiles_i = (A.ni + kHStripOut - 1) / kHStripOut;
     A.ntiles = A.tiles_i * ((A.nj + kHStripRows - 1) / kHStripRows);
     const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);

@@ -123,6 +123,137 @@ __device__ __forceinline__ void hdiff_strip(const StepArgs<T>& A, int t, int k) 
   for (int s = 0; s < PD; ++s) step(n + s, s, false);
 }
 
+// FP32: two adjacent columns per lane (a = 120 s - 4 + 2 l, b = a + 1), 128
+// columns per wave of which lanes 2..61 own the strip's 120 output columns
+// (15 bytes of a mask row).  The east neighbour of a and the west neighbour
+// of b are in the lane itself, so a row needs half the shifts; the two
+// columns' limiter bits come from two ballots, interleaved into the row's
+// bytes.  Same values and bits as hdiff_strip.
+constexpr int kHStripOut2 = 120;
+
+// bits 0..3 of v to bits 0, 2, 4, 6
+__device__ __forceinline__ uint32_t spread4(uint32_t v) {
+  return (v & 1u) | ((v & 2u) << 1) | ((v & 4u) << 2) | ((v & 8u) << 3);
+}
+
+template <int TJ, int PD>
+__device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, int k) {
+  static_assert((TJ + 4) % PD == 0, "the row walk is unrolled by the prefetch depth");
+  using T = float;
+  constexpr uint32_t S = 4;
+  const int lane = threadIdx.x & 63;
+  const int si = t % A.tiles_i, sj = t / A.tiles_i;
+  const int ni = A.ni, nj = A.nj;
+  const int ia = kHStripOut2 * si - 4 + 2 * lane, ib = ia + 1;  // lane 2's a is the first output column
+  const int j0 = TJ * sj;
+  const bool owna = lane >= 2 && lane < 2 + kHStripOut2 / 2 && ia < ni;
+  const bool ownb = lane >= 2 && lane < 2 + kHStripOut2 / 2 && ib < ni;
+  const bool has_mask = A.mask != nullptr;
+  const T coeff = A.coeff;
+
+  const auto row_rsrc = [&](const char* base, int64_t row_bytes, int r, int rows, uint32_t width) {
+    const bool in = r >= 0 && r < rows;
+    return make_rsrc(base + (in ? (int64_t)r * row_bytes : 0), in ? width : 0u);
+  };
+  const char* ubase = reinterpret_cast<const char*>(A.u) + ((int64_t)k * A.u_sk - 2 - 2 * A.u_sj) * S;
+  const char* obase = reinterpret_cast<const char*>(A.out) + (int64_t)k * A.o_sk * S;
+  const uint32_t ua_off = (ia >= -2 && ia < ni + 2) ? (uint32_t)(ia + 2) * S : kOffNone;  // window: ni + 4
+  const uint32_t ub_off = (ib >= -2 && ib < ni + 2) ? (uint32_t)(ib + 2) * S : kOffNone;
+  const uint32_t oa_off = owna ? (uint32_t)ia * S : kOffNone;  // window: ni
+  const uint32_t ob_off = ownb ? (uint32_t)ib * S : kOffNone;
+  // limiter bytes: one descriptor over the whole mask (below 4 GiB), lanes
+  // 0..14 the x bytes of a row, lanes 16..30 its y bytes
+  const auto rm = make_rsrc(A.mask, has_mask ? (uint32_t)A.ml.total : 0u);
+  const int64_t W = A.ml.words, plane_xy = (int64_t)nj * W * 8;
+  const int64_t x_lev = A.ml.x_off + (int64_t)k * plane_xy, y_lev = A.ml.y_off + (int64_t)k * plane_xy;
+  const int mb = lane & 15;  // the lane's byte of the strip's 15
+  const bool xlane = lane < 15, ylane = lane >= 16 && lane < 31;
+  const uint32_t mcol = (uint32_t)(kHStripOut2 / 8 * si + mb);
+  const bool mcol_in = mcol < (uint32_t)(W * 8);
+  const int bshift = 2 + 4 * mb;  // byte mb holds columns 8 mb .. 8 mb + 7: lanes 2 + 4 mb .. 5 + 4 mb
+  const uint32_t ex_base = (uint32_t)(A.ml.ex_off + (int64_t)k * nj), ey_base = (uint32_t)(A.ml.ey_off + (int64_t)k * ni);
+
+  T pa[PD], pb[PD];
+  const int r0 = j0 - 2;
+  constexpr int NR = TJ + 4;
+  auto issue = [&](int r, int s) {
+    const auto ru = row_rsrc(ubase, A.u_sj * S, r + 2, nj + 4, (uint32_t)(ni + 4) * S);
+    pa[s] = buf_ld(ru, ua_off, T());
+    pb[s] = buf_ld(ru, ub_off, T());
+  };
+
+  T u1a = 0, u1b = 0, u2a = 0, u2b = 0, lap2a = 0, lap2b = 0, Fx2a = 0, Fx2b = 0, Fy3a = 0, Fy3b = 0;
+  auto step = [&](int n, int s, bool refill) {
+    const int R = r0 + n;
+    T uRa = pa[s], uRb = pb[s];
+    asm volatile("" : "+v"(uRa), "+v"(uRb));  // copies of their own: the slots are free for the refill
+    if (refill) issue(R + PD, s);
+    // the shifts run with every lane active (a disabled lane would read as 0)
+    const T u1a_e = lane_shift<kDppWaveShl1>(u1a);  // east of b
+    const T u1b_w = lane_shift<kDppWaveShr1>(u1b);  // west of a
+    const T lap1a = T(4) * u1a - ((u1b_w + u1b) + (u2a + uRa));  // lap(R-1)
+    const T lap1b = T(4) * u1b - ((u1a + u1a_e) + (u2b + uRb));
+    const T lap1a_e = lane_shift<kDppWaveShl1>(lap1a);
+    const T Fx2b_w = lane_shift<kDppWaveShr1>(Fx2b);
+    const T fxa = lap1b - lap1a, fxb = lap1a_e - lap1b;  // x fluxes of row R-1
+    const bool kxa = flux_kept(fxa, u1b - u1a), kxb = flux_kept(fxb, u1a_e - u1b);
+    const T Fx1a = kxa ? fxa : T(0), Fx1b = kxb ? fxb : T(0);
+    const T fya = lap1a - lap2a, fyb = lap1b - lap2b;  // y fluxes between rows R-2 and R-1
+    const bool kya = flux_kept(fya, u1a - u2a), kyb = flux_kept(fyb, u1b - u2b);
+    const T Fy2a = kya ? fya : T(0), Fy2b = kyb ? fyb : T(0);
+    const int q = R - 2;  // out(R-2)
+    const T va = u2a - coeff * ((Fx2a - Fx2b_w) + (Fy2a - Fy3a));
+    const T vb = u2b - coeff * ((Fx2b - Fx2a) + (Fy2b - Fy3b));
+    const bool qrow = q >= j0 && q < j0 + TJ;  // uniform
+    if (qrow) {
+      const auto ro = row_rsrc(obase, A.o_sj * S, q, nj, (uint32_t)ni * S);
+      buf_st(ro, oa_off, va);
+      buf_st(ro, ob_off, vb);
+    }
+    if (has_mask) {
+      const int rx = R - 1;
+      const uint64_t bxa = __ballot(owna && kxa), bxb = __ballot(ownb && kxb);
+      const uint64_t bya = __ballot(owna && kya), byb = __ballot(ownb && kyb);
+      const bool xrow = rx >= j0 && rx < j0 + TJ && rx < nj, yrow = qrow && q < nj;  // uniform
+      const uint64_t ba = ylane ? bya : bxa, bb = ylane ? byb : bxb;
+      const uint8_t byte = (uint8_t)(spread4((uint32_t)(ba >> bshift) & 15u) | (spread4((uint32_t)(bb >> bshift) & 15u) << 1));
+      uint32_t off = kOffNone;
+      if (xlane && xrow && mcol_in) off = (uint32_t)(x_lev + (int64_t)rx * W * 8) + mcol;
+      if (ylane && yrow && mcol_in) off = (uint32_t)(y_lev + (int64_t)q * W * 8) + mcol;
+      buf_st_u8(rm, off, byte);
+      // the x flux at i = -1 (column b of lane 1 in the first strip) and the
+      // y flux below row 0 have byte planes of their own
+      if (si == 0 && xrow && rx >= 0) buf_st_u8(rm, ib == -1 ? ex_base + (uint32_t)rx : kOffNone, kxb ? 1 : 0);
+      if (q == -1) {
+        buf_st_u8(rm, owna ? ey_base + (uint32_t)ia : kOffNone, kya ? 1 : 0);
+        buf_st_u8(rm, ownb ? ey_base + (uint32_t)ib : kOffNone, kyb ? 1 : 0);
+      }
+    }
+    Fy3a = Fy2a; Fy3b = Fy2b;
+    Fx2a = Fx1a; Fx2b = Fx1b;
+    lap2a = lap1a; lap2b = lap1b;
+    u2a = u1a; u2b = u1b;
+    u1a = uRa; u1b = uRb;
+  };
+
+#pragma unroll
+  for (int s = 0; s < PD; ++s) issue(r0 + s, s);
+  int n = 0;
+  for (; n < NR - PD; n += PD) {
+#pragma unroll
+    for (int s = 0; s < PD; ++s) step(n + s, s, true);
+  }
+#pragma unroll
+  for (int s = 0; s < PD; ++s) step(n + s, s, false);
+}
+
+__global__ void __launch_bounds__(kWG) k_hdiff_strip2(StepArgs<float> A) {
+  const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
+                                               (int)(threadIdx.x >> 6));
+  if (t >= A.ntiles) return;  // whole waves only: no barrier follows
+  hdiff_strip2<kHStripRows, kHStripPD>(A, t, blockIdx.y);
+}
+
 // One strip per wave, at one level per grid row.
 template <typename T>
 __global__ void __launch_bounds__(kWG) k_hdiff_strip(StepArgs<T> A) {

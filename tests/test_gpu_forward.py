@@ -33,7 +33,10 @@ def _opts(impl, tile=0, col=0, dtype=torch.float64, dom=None, op=api.OP_STEP):
 
 
 # ------------------------------------------------------------------ hdiff
-HDIFF_CASES = [(64, 64, 16), (67, 45, 7), (1, 1, 1), (130, 3, 5), (5, 130, 3), (2, 2, 2)]
+# the standalone hdiff walks strips of 56 (FP64) or 120 (FP32) columns and
+# 16 rows: domains ending on and one past those edges too
+HDIFF_CASES = [(64, 64, 16), (67, 45, 7), (1, 1, 1), (130, 3, 5), (5, 130, 3), (2, 2, 2), (56, 16, 2), (57, 17, 2),
+               (120, 9, 2), (121, 33, 2), (240, 3, 2), (241, 5, 2)]
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
