@@ -234,6 +234,55 @@ def test_p9_hand_solved_columns(oracle):
             assert abs(lam[k] - float(refT[k])) <= 4e-16 * max(1.0, abs(float(refT[k])))
 
 
+# ---------------------------------------------------------------- the step's forcing term
+# Inside the step the right-hand side of each column is d_k = u_k + data_k
+# with u_k the diffused field (the implicit vertical advection of the
+# benchmark, its right-hand side taken from the horizontal stage).  These pins
+# compose the step from pieces pinned above (hdiff: closed forms; the column
+# solve: dense LU, Cramer's rule) and check the forcing enters with its sign.
+def test_step_forcing_at_zero_velocity_is_added_once(oracle):
+    # w = 0 makes T the identity: the new interior is the diffused field plus
+    # data, bit for bit (one rounding, in the same order as the definition)
+    f = inputs.fields_sized(9, 7, 5, seed=41)
+    w0 = np.zeros_like(f.w)
+    nxt, mx, my = oracle.step(f.u, f.data, w0, COEFF, DT_DZ)
+    h, hmx, hmy = oracle.hdiff(f.u, COEFF)
+    assert np.array_equal(_interior(nxt), _interior(h) + f.data)
+    assert np.array_equal(mx, hmx) and np.array_equal(my, hmy)
+    # the halo is carried from u, not diffused or forced
+    nxt[:, 2:-2, 2:-2] = 0.0
+    ref = f.u.copy()
+    ref[:, 2:-2, 2:-2] = 0.0
+    assert np.array_equal(nxt, ref)
+    # data = 0 leaves the diffused field itself; doubling data doubles the
+    # increment exactly (data ~ U[-0.1, 0.1] doubles without rounding)
+    n0, _, _ = oracle.step(f.u, np.zeros_like(f.data), w0, COEFF, DT_DZ)
+    assert np.array_equal(_interior(n0), _interior(h))
+    n2, _, _ = oracle.step(f.u, 2.0 * f.data, w0, COEFF, DT_DZ)
+    assert np.array_equal(_interior(n2), _interior(h) + 2.0 * f.data)
+
+
+def test_step_is_vadv_of_hdiff_with_forcing(oracle):
+    # random w and non-zero data: the step equals vadv applied to hdiff's
+    # interior with the same forcing, bit for bit, and each column solves the
+    # dense tridiagonal system written out from its definition
+    ni, nj, nk = 7, 6, 9
+    f = inputs.fields_sized(ni, nj, nk, seed=42)
+    assert np.max(np.abs(f.data)) > 0.05
+    nxt, _, _ = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    h, _, _ = oracle.hdiff(f.u, COEFF)
+    x = oracle.vadv(_interior(h), f.data, f.w, DT_DZ)
+    assert np.array_equal(_interior(nxt), x)
+    for j in range(nj):
+        for i in range(ni):
+            T = _dense_T(f.w[:, j, i], DT_DZ)
+            ref = np.linalg.solve(T, _interior(h)[:, j, i] + f.data[:, j, i])
+            np.testing.assert_allclose(_interior(nxt)[:, j, i], ref, rtol=0, atol=1e-14)
+            # and not the unforced or oppositely forced solve
+            bad = np.linalg.solve(T, _interior(h)[:, j, i] - f.data[:, j, i])
+            assert np.max(np.abs(_interior(nxt)[:, j, i] - bad)) > 1e-6
+
+
 # ---------------------------------------------------------------- independent pure-Python copy
 def test_pure_python_copy_agrees(oracle):
     f = inputs.fields_sized(6, 5, 3, seed=50)
