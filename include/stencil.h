@@ -1,8 +1,10 @@
 /*
  * stencil.h -- C ABI of the MI355X (gfx950) stencil library (libgt4mi.so).
  *
- * What is computed (GT4Py paper, Sec. 3.1: the two benchmark stencils, a
- * multi-stage horizontal diffusion and an implicit vertical advection):
+ * What is computed: the two benchmark stencils the GT4Py paper names in
+ * Sec. 3.1, a multi-stage horizontal diffusion and an implicit vertical
+ * advection.  The paper prints no formulas; these are the benchmark
+ * workload's definitions of the two stencils, taken literally:
  *
  *   horizontal diffusion (hdiff), per level k, over the interior I:
  *     lap(i,j) = 4u(i,j) - u(i-1,j) - u(i+1,j) - u(i,j-1) - u(i,j+1)
@@ -114,7 +116,7 @@ typedef enum {
 
 /* Optional per-call options; pass NULL for defaults. */
 /* Form of the horizontal diffusion's Laplacian stage (Sec. 3.1 names the
- * stencil; its benchmark definition is the STATED form).  The DAMPING form
+ * stencil; the workload's definition of it is the STATED form).  The DAMPING form
  * takes the discrete Laplacian itself, so that with every flux kept the
  * update is u - coeff * (discrete Laplacian applied twice), fourth-order
  * damping, where the stated form adds that term.  The limiter rule and the
@@ -189,7 +191,7 @@ size_t stencil_workspace_bytes(int op, stencil_dtype dtype, const int64_t domain
                                const stencil_options* opts);
 
 /* ------------------------------------------------------------- forward */
-/* Horizontal diffusion (Sec. 3.1).  u: read on the domain plus a 2-point
+/* Horizontal diffusion (named in Sec. 3.1; formulas above).  u: read on the domain plus a 2-point
  * halo in i and j.  out: the interior is written, its halo is untouched.
  * mask: NULL, or stencil_mask_bytes(domain) device bytes that receive the
  * limiter decisions.  opts->hdiff_form and opts->coeff_field select the
@@ -198,7 +200,7 @@ int stencil_hdiff(stencil_dtype dtype, const stencil_field* u, stencil_field* ou
                   const int64_t domain[3], double coeff, void* mask,
                   const stencil_options* opts, hipStream_t stream);
 
-/* Vertical advection (Sec. 3.1): out = T(w)^{-1} (u + data) per column.
+/* Vertical advection (named in Sec. 3.1; formulas above): out = T(w)^{-1} (u + data) per column.
  * u, data: domain; w: nk+1 staggered levels (w_0 and w_nk are not read);
  * out: domain (interior only). */
 int stencil_vadv(stencil_dtype dtype, const stencil_field* u, const stencil_field* data,

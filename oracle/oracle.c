@@ -15,9 +15,11 @@
  *     evaluated over the whole domain before it is stored (so the output
  *     never aliases the input); temporaries are not observable; the
  *     iteration space comes from domain/origin.
- *   - The two benchmark stencils named in Sec. 3.1 (Fig. 3): the multi-stage
- *     horizontal diffusion and the vertical advection implicit solver.  The
- *     formulas below are the benchmark definitions of those two stencils:
+ *   - The two benchmark stencils the paper names in Sec. 3.1: the
+ *     multi-stage horizontal diffusion and the vertical advection implicit
+ *     solver.  The paper prints no formula for either; the formulas below
+ *     are the benchmark workload's definition of the two stencils, taken
+ *     literally:
  *       lap  = 4u - u[i-1] - u[i+1] - u[j-1] - u[j+1]
  *       flx  = lap[i+1] - lap[i], zeroed where flx * (u[i+1]-u[i]) > 0
  *       fly  = the same along j
@@ -69,7 +71,7 @@
 #define MXIDX(i, j, k) ((size_t)(k) * (size_t)nj * (size_t)(ni + 1) + (size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1))
 #define MYIDX(i, j, k) ((size_t)(k) * (size_t)(nj + 1) * (size_t)ni + (size_t)((j) + 1) * (size_t)ni + (size_t)(i))
 
-/* The limiter (benchmark definition, Sec. 3.1): the flux is zeroed where
+/* The limiter (the workload's definition of the diffusion): the flux is zeroed where
  * flux * gradient > 0, the product taken literally in the precision of the
  * decision (binary64, or binary32 when decide_f32 is set). */
 static int limiter_keeps(double f, double g) { return !(f * g > 0.0); }
@@ -95,7 +97,7 @@ static float lap32(const double* u, int ni, int nj, int i, int j, int k, int dam
 }
 
 /* ------------------------------------------------------------------ */
-/* Limiter masks of the horizontal diffusion (Sec. 3.1 benchmark)        */
+/* Limiter masks of the horizontal diffusion (workload definition)       */
 /* ------------------------------------------------------------------ */
 void oracle_hdiff_masks_form(int ni, int nj, int nk, const double* u, int decide_f32, int damping,
                              unsigned char* mx, unsigned char* my) {
@@ -211,7 +213,7 @@ void oracle_hdiff(int ni, int nj, int nk, const double* u, double coeff, int dec
 }
 
 /* ------------------------------------------------------------------ */
-/* Vertical advection (Sec. 3.1 benchmark): tridiagonal system per      */
+/* Vertical advection (workload definition): tridiagonal system per     */
 /* column; the boundary rows (intervals, Sec. 2.2) have a_0 = 0 and     */
 /* c_{nk-1} = 0.  Thomas algorithm: FORWARD elimination then BACKWARD   */
 /* substitution (Sec. 2.2 vertical iteration orders).                   */

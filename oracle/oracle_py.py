@@ -1,8 +1,9 @@
 """Pure-Python loop version of the forward stencils, for tiny domains only.
 
 TEST INFRASTRUCTURE ONLY.  A second, independently written CPU reference of
-the horizontal diffusion and the vertical Thomas solve (Sec. 3.1 benchmark
-stencils), used to cross-check ``oracle.c`` on domains of a few hundred
+the horizontal diffusion and the vertical Thomas solve (the benchmark
+stencils named in Sec. 3.1, with the workload's definition of their
+formulas, which the paper does not print), used to cross-check ``oracle.c`` on domains of a few hundred
 points.  Same array conventions as ``oracle.py``.
 """
 from __future__ import annotations

@@ -111,9 +111,13 @@ int check_field(const char* name, const stencil_field* f, const int64_t* dom, Ro
                 (long long)f->stride[1], (long long)f->shape[0]);
   if (f->stride[2] < f->stride[1] * f->shape[1] || f->stride[2] >= (int64_t(1) << 46))
     return fail(STENCIL_E_STRIDE, "%s.stride[2] = %lld overlaps planes", name, (long long)f->stride[2]);
-  // kernels address within a level with 32-bit byte offsets
-  if ((f->stride[1] * f->shape[1] + f->shape[0]) * (int64_t)es >= (int64_t(1) << 32))
-    return fail(STENCIL_E_UNSUPPORTED, "%s: one level spans 4 GiB or more", name);
+  // kernels address within a level with 32-bit byte offsets, and predicate a
+  // lane's access off with the offset kOffNone, which must stay outside every
+  // window: a level may span at most kOffNone - 16 bytes
+  if ((f->stride[1] * f->shape[1] + f->shape[0]) * (int64_t)es > (int64_t)kOffNone - 16)
+    return fail(STENCIL_E_UNSUPPORTED, "%s: one level spans %lld bytes, above the 32-bit window limit %lld", name,
+                (long long)((f->stride[1] * f->shape[1] + f->shape[0]) * (int64_t)es),
+                (long long)((int64_t)kOffNone - 16));
   const int64_t h = (role == ROLE_HALO) ? kHalo : 0;
   for (int d = 0; d < 2; ++d) {
     if (f->origin[d] < h)

@@ -164,8 +164,8 @@ struct LevelCursor {
 };
 
 // ------------------------------------------------------------ limiter
-// The flux is zeroed where flux * gradient > 0 (Sec. 3.1 benchmark
-// definition), the product taken literally in the working precision.
+// The flux is zeroed where flux * gradient > 0 (the workload's definition
+// of the diffusion named in Sec. 3.1), the product taken literally in the working precision.
 template <typename T>
 __device__ __forceinline__ bool flux_kept(T f, T g) {
   return !(f * g > T(0));

@@ -144,6 +144,30 @@ def test_strides(L):
     assert step(L, u, data, w, out, d) == code("STENCIL_E_STRIDE")
 
 
+def test_level_window_limit(L):
+    # kernels predicate a lane's access off with the byte offset 0xFFFFFFF0,
+    # which must lie outside every level window: an FP32 output one point
+    # wide whose level spans 0xFFFFFFF0 bytes (below 4 GiB) is refused
+    u, data, w, out, d = fields(ni=1, nj=1, nk=1)
+    rows = (0xFFFFFFF0 // 4 - 5) // 5
+    assert (5 * rows + 5) * 4 == 0xFFFFFFF0
+    out = _lib.StencilField()
+    out.data = BASE + (1 << 36)
+    out.shape = _lib.I64x3(5, rows, 1)
+    out.stride = _lib.I64x3(1, 5, 5 * rows)
+    out.origin = _lib.I64x3(2, 2, 0)
+    assert step(L, u, data, w, out, d, dt=_lib.F32) == code("STENCIL_E_UNSUPPORTED")
+    assert "window" in _lib.last_error()
+    # 16 bytes less passes that check (and fails a later one: an origin that
+    # puts the domain past the field's end)
+    out.shape = _lib.I64x3(5, rows - 1, 1)
+    out.stride = _lib.I64x3(1, 5, 5 * rows)
+    assert (5 * (rows - 1) + 5) * 4 <= 0xFFFFFFF0 - 16
+    out.origin = _lib.I64x3(5, 2, 0)
+    assert step(L, u, data, w, out, d, dt=_lib.F32) in (code("STENCIL_E_HALO"), code("STENCIL_E_SHAPE"))
+    assert "window" not in _lib.last_error()
+
+
 def test_alias(L):
     u, data, w, out, d = fields()
     out.data = u.data  # in-place is forbidden (whole-domain assignment semantics)

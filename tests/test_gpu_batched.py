@@ -1,7 +1,7 @@
 """GPU parity of the persistent batched launches.
 
 The uneven 32-field workload (inputs.batch_fields: ni, nj in [48, 384], nk
-in [40, 136]) runs as one forward launch and one adjoint pair; every field
+in [40, 137] inclusive) runs as one forward launch and one adjoint pair; every field
 is checked against the oracle, and bit for bit against separate
 single-field launches, which solve each column with the same two-ended
 elimination.  Masks are compared bit for bit.  Smaller batches cover empty
