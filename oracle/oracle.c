@@ -54,12 +54,20 @@
  * so that a binary32 implementation and this reference branch identically.
  * All values are always carried in FP64.
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC; a second
+ * build adds -fopenmp for the CPU baseline on all host cores.  Its parallel
+ * regions split independent levels (horizontal stages) or independent
+ * columns (the tridiagonal solves) over threads, each with its own
+ * temporaries, so every value is computed by the same operations in the
+ * same order and both builds give identical results.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------ */
 /* indexing helpers                                                     */
@@ -101,6 +109,7 @@ static float lap32(const double* u, int ni, int nj, int i, int j, int k, int dam
 /* ------------------------------------------------------------------ */
 void oracle_hdiff_masks_form(int ni, int nj, int nk, const double* u, int decide_f32, int damping,
                              unsigned char* mx, unsigned char* my) {
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nk; ++k) {
     /* x-fluxes on [-1, ni) x [0, nj) */
     for (int j = 0; j < nj; ++j)
@@ -156,12 +165,15 @@ static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coe
                              const double* kappa, int damping, const unsigned char* mx,
                              const unsigned char* my, double* out_interior) {
   const int li = ni + 2, lj = nj + 2; /* lap on the box [-1,ni] x [-1,nj] */
+#pragma omp parallel
+  { /* levels are independent: one set of level temporaries per thread */
   double* lap = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
   double* fx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)nj);
   double* fy = (double*)malloc(sizeof(double) * (size_t)ni * (size_t)(nj + 1));
 #define LAP(i, j) lap[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)]
 #define FX(i, j) fx[(size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1)]
 #define FY(i, j) fy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)]
+#pragma omp for schedule(static)
   for (int k = 0; k < nk; ++k) {
     for (int j = -1; j <= nj; ++j)
       for (int i = -1; i <= ni; ++i) LAP(i, j) = lap64(u, ni, nj, i, j, k, damping);
@@ -187,6 +199,7 @@ static void hdiff_with_masks(int ni, int nj, int nk, const double* u, double coe
   free(lap);
   free(fx);
   free(fy);
+  }
 }
 
 /* Forward horizontal diffusion, general form: per-point coefficient kappa
@@ -229,8 +242,11 @@ static double coef_c(const double* w, int ni, int nj, int nk, int i, int j, int 
 /* x = T^{-1} d per column, d[k] given (interior layout). */
 static void thomas_columns(int ni, int nj, int nk, const double* d, const double* w, double dt_dz,
                            double* x) {
+#pragma omp parallel
+  { /* columns are independent: one pair of column temporaries per thread */
   double* cp = (double*)malloc(sizeof(double) * (size_t)nk + 8);
   double* dp = (double*)malloc(sizeof(double) * (size_t)nk + 8);
+#pragma omp for schedule(static)
   for (int j = 0; j < nj; ++j)
     for (int i = 0; i < ni; ++i) {
       for (int k = 0; k < nk; ++k) {
@@ -252,6 +268,7 @@ static void thomas_columns(int ni, int nj, int nk, const double* d, const double
     }
   free(cp);
   free(dp);
+  }
 }
 
 /* vadv alone: right-hand side d = u_in + data, all interior layout. */
@@ -278,8 +295,10 @@ void oracle_step_gen(int ni, int nj, int nk, const double* u, const double* data
   double* h = (double*)malloc(sizeof(double) * n);
   double* x = (double*)malloc(sizeof(double) * n);
   hdiff_with_masks(ni, nj, nk, u, coeff, kappa, damping, mx, my, h);
+#pragma omp parallel for schedule(static)
   for (size_t p = 0; p < n; ++p) h[p] += data[p];
   thomas_columns(ni, nj, nk, h, w, dt_dz, x);
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nk; ++k)
     for (int j = 0; j < nj; ++j)
       for (int i = 0; i < ni; ++i) next[UIDX(i, j, k)] = x[IIDX(i, j, k)];
@@ -304,6 +323,8 @@ void oracle_hdiff_adjoint_gen(int ni, int nj, int nk, const double* lam, const u
                               const unsigned char* my, double coeff, const double* kappa,
                               int damping, double* ubar) {
   const int li = ni + 2, lj = nj + 2;
+#pragma omp parallel
+  { /* levels are independent: one set of level temporaries per thread */
   double* gx = (double*)malloc(sizeof(double) * (size_t)(ni + 1) * (size_t)(nj > 0 ? nj : 1));
   double* gy = (double*)malloc(sizeof(double) * (size_t)(ni > 0 ? ni : 1) * (size_t)(nj + 1));
   double* lb = (double*)malloc(sizeof(double) * (size_t)li * (size_t)lj);
@@ -313,6 +334,7 @@ void oracle_hdiff_adjoint_gen(int ni, int nj, int nk, const double* lam, const u
 #define GX(i, j) ((((i) >= -1 && (i) < ni && (j) >= 0 && (j) < nj)) ? gx[(size_t)(j) * (size_t)(ni + 1) + (size_t)((i) + 1)] : 0.0)
 #define GY(i, j) ((((i) >= 0 && (i) < ni && (j) >= -1 && (j) < nj)) ? gy[(size_t)((j) + 1) * (size_t)ni + (size_t)(i)] : 0.0)
 #define LB(i, j) ((((i) >= -1 && (i) <= ni && (j) >= -1 && (j) <= nj)) ? lb[(size_t)((j) + 1) * (size_t)li + (size_t)((i) + 1)] : 0.0)
+#pragma omp for schedule(static)
   for (int k = 0; k < nk; ++k) {
     /* out(p) = u(p) - coeff(p) * (Fx(p) - Fx(p-ei) + Fy(p) - Fy(p-ej)):
      * dout(p)/dFx(q) = -coeff(p) if q == p, +coeff(p) if q == p - ei, so
@@ -353,6 +375,7 @@ void oracle_hdiff_adjoint_gen(int ni, int nj, int nk, const double* lam, const u
   free(gx);
   free(gy);
   free(lb);
+  }
 }
 
 void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsigned char* mx,
@@ -366,8 +389,11 @@ void oracle_hdiff_adjoint(int ni, int nj, int nk, const double* lam, const unsig
 void oracle_vadv_adjoint(int ni, int nj, int nk, const double* xbar, const double* w, double dt_dz,
                          double* lam) {
   if (ni <= 0 || nj <= 0 || nk <= 0) return;
+#pragma omp parallel
+  { /* columns are independent: one pair of column temporaries per thread */
   double* al = (double*)malloc(sizeof(double) * (size_t)nk);
   double* be = (double*)malloc(sizeof(double) * (size_t)nk);
+#pragma omp for schedule(static)
   for (int j = 0; j < nj; ++j)
     for (int i = 0; i < ni; ++i) {
       for (int k = 0; k < nk; ++k) {
@@ -391,6 +417,7 @@ void oracle_vadv_adjoint(int ni, int nj, int nk, const double* xbar, const doubl
     }
   free(al);
   free(be);
+  }
 }
 
 /* Step adjoint: lam = T^{-T} xbar; ubar = J_h^T lam; databar = lam. */
@@ -596,3 +623,12 @@ void oracle_w_grad(int ni, int nj, int nk, const double* w, const double* x, con
 }
 
 int oracle_version(void) { return 2; }
+
+/* Threads a parallel region of this build uses: 1 unless built with OpenMP. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

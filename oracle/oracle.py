@@ -18,6 +18,7 @@ binary32 inputs.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -27,30 +28,57 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP: independent levels / columns over the
+# host's threads, identical arithmetic (CPU baseline on all cores)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-shared", "-fPIC"]
 
 
+def _build_one(path: str, extra) -> None:
+    tmp = path + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", *CFLAGS, *extra, _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (plain loops, no FP contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile liboracle.so (and its OpenMP twin) with gcc: plain loops, no
+    FP contraction."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            _build_one(path, extra)
     return _LIB
 
 
-_lib = None
+_libs = {}
+_threaded = False
+
+
+@contextlib.contextmanager
+def threaded():
+    """Oracle calls inside the block run on the OpenMP build (all threads
+    OMP_NUM_THREADS allows); results are identical to the serial build."""
+    global _threaded
+    prev, _threaded = _threaded, True
+    try:
+        yield lib()
+    finally:
+        _threaded = prev
+
+
+def threads() -> int:
+    """Threads a parallel region of the current build uses."""
+    return int(lib().oracle_threads())
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    path = _LIB_OMP if _threaded else _LIB
+    if path not in _libs:
         # (re)build when missing or older than its source, so a stale
         # library never answers for the current definitions
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _build_one(path, ["-fopenmp"] if path == _LIB_OMP else [])
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         bp = ctypes.POINTER(ctypes.c_ubyte)
         I, D = ctypes.c_int, ctypes.c_double
@@ -87,8 +115,10 @@ def lib():
         L.oracle_coeff_grad.restype = D
         L.oracle_coeff_grad_form.argtypes = [I, I, I, dp, dp, bp, bp, I]
         L.oracle_coeff_grad_form.restype = D
-        _lib = L
-    return _lib
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = I
+        _libs[path] = L
+    return _libs[path]
 
 
 def _d(a):

@@ -78,6 +78,46 @@ def test_per_step_consistency_with_oracle(dtype):
         state = round_f32(nxt) if r32 else nxt
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_graph_loop_full_size_per_step_gate(dtype):
+    """The 100-step loop at 512x512x80 gated per step on its own states:
+    a graph of n + 1 steps leaves state n in one ping-pong buffer and state
+    n + 1 in the other, and the oracle applied to GPU state n must give GPU
+    state n + 1 (1e-12 FP64, 2e-5 FP32 against the oracle fed the binary32
+    state and inputs with binary32 limiter decisions), at n = 1, 50, 99."""
+    wl = inputs.STEP_512
+    ni, nj, nk = wl.ni, wl.nj, wl.nk
+    dims = (ni, nj, nk)
+    f = inputs.fields_for(wl)
+    r32 = dtype == torch.float32
+    data_r = round_f32(f.data) if r32 else f.data
+    w_r = round_f32(f.w) if r32 else f.w
+    coeff = c_scalar(inputs.COEFF, dtype)
+    u_a, data, w = dev_fields(f, dtype, DEV)
+    u_b = fields.from_padded(f.u, dtype, DEV)
+    s = torch.cuda.Stream()
+    for n in (1, 50, 99):
+        print(f"per-step gate 512x512x80 {dtype}: graph of {n + 1} steps", flush=True)
+        for buf in (u_a, u_b):
+            fields.padded(buf, ni, nj, nk).copy_(torch.as_tensor(f.u, device=DEV).to(dtype))
+        torch.cuda.synchronize()
+        g = api.stencil_graph_capture_steps(n + 1, u_a, u_b, data, w, dims, inputs.COEFF, inputs.DT_DZ, stream=s)
+        try:
+            api.stencil_graph_launch(g, stream=s)
+            s.synchronize()
+        finally:
+            api.stencil_graph_destroy(g)
+        # step m writes u_b for even m (0-based), u_a for odd m
+        last, prev = (u_b, u_a) if n % 2 == 0 else (u_a, u_b)
+        state_n = host(fields.padded(prev, ni, nj, nk))
+        state_n1 = host(fields.interior(last, ni, nj, nk))
+        assert np.isfinite(state_n1).all()
+        nxt, _, _ = orc.step(state_n, data_r, w_r, coeff, inputs.DT_DZ, decide_f32=r32)
+        err = rel_err(state_n1, nxt[:, 2:-2, 2:-2])
+        print(f"  step {n} -> {n + 1}: rel err {err:.3e}", flush=True)
+        assert err <= TOL[dtype], (n, err)
+
+
 def test_graph_capture_full_size_100_steps():
     """The 100-step loop at 512x512x80 FP64: graph replay == eager, bitwise."""
     wl = inputs.STEP_512

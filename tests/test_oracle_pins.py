@@ -531,3 +531,27 @@ def test_periodic_diffusion_conserves_mass(oracle):
         u = oracle.halo_periodic(nxt)
     s1 = math.fsum(_interior(u).ravel())
     assert abs(s1 - s0) <= 1e-13 * math.fsum(np.abs(_interior(u)).ravel())
+
+
+def test_openmp_build_is_identical_to_serial(oracle):
+    """The CPU baseline's OpenMP build splits independent levels and columns
+    over threads with per-thread temporaries; every result must equal the
+    serial build's bit for bit (same operations, same order)."""
+    ni, nj, nk = 37, 29, 23
+    f = inputs.fields_sized(ni, nj, nk, seed=950)
+    ob = inputs.cotangent(ni, nj, nk)
+    kap = inputs.coeff_field(ni, nj, nk)
+    ser = [oracle.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ, kappa=kap, damping=True),
+           oracle.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ, decide_f32=True)]
+    ser_adj = oracle.step_adjoint(ob, f.w, ser[0][1], ser[0][2], inputs.COEFF, inputs.DT_DZ, kappa=kap)
+    with oracle.threaded():
+        assert oracle.threads() >= 1
+        par = [oracle.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ, kappa=kap, damping=True),
+               oracle.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ, decide_f32=True)]
+        par_adj = oracle.step_adjoint(ob, f.w, ser[0][1], ser[0][2], inputs.COEFF, inputs.DT_DZ, kappa=kap)
+    assert oracle.threads() == 1
+    for a, b in zip(ser, par):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    for x, y in zip(ser_adj, par_adj):
+        assert np.array_equal(x, y)
