@@ -352,6 +352,23 @@ int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
                                  size_t ws_bytes, const stencil_options* opts,
                                  hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward batch of stencil_step_batched with its work list in a fixed
+ * device array of STENCIL_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each device it runs on until the process ends, instead of a
+ * caller workspace.  The call allocates no device memory.  Arguments,
+ * validation, results (bit for bit) and limits are those of
+ * stencil_step_batched; a batch whose work list
+ * (stencil_batch_workspace_bytes) is larger than the array is refused with
+ * STENCIL_E_UNSUPPORTED (any batch of up to 256 fields fits).  Every call
+ * on a device uses that device's one array: calls that may run at the same
+ * time on one device (two streams, two threads, two graphs) race, and the
+ * caller must order them. */
+#define STENCIL_NOALLOC_SCRATCH_BYTES 65536
+int stencil_step_batched_noalloc(stencil_dtype dtype, int n, const stencil_batch_item* items,
+                                 const stencil_options* opts, hipStream_t stream);
+
 /* ---------------------------------------------------------- hipGraph loop */
 typedef struct stencil_graph stencil_graph;
 

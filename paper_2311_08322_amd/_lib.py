@@ -30,6 +30,9 @@ ERRORS = {
 }
 CODES = {v: k for k, v in ERRORS.items()}
 
+# size of the library's fixed work-list array (stencil_step_batched_noalloc)
+NOALLOC_SCRATCH_BYTES = 65536
+
 IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN = 0, 1, 2
 COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF, COLUMN_SPLIT = 0, 1, 2, 3
 BOUNDARY_FROZEN, BOUNDARY_PERIODIC = 0, 1
@@ -125,6 +128,7 @@ SIGNATURES = {
     "stencil_batch_adjoint_workspace_bytes": (SZ, [I, I, ctypes.POINTER(StencilBatchAdjointItem)]),
     "stencil_step_batched": (I, [I, I, ctypes.POINTER(StencilBatchItem), VP, SZ, PO, VP]),
     "stencil_step_adjoint_batched": (I, [I, I, ctypes.POINTER(StencilBatchAdjointItem), VP, SZ, PO, VP]),
+    "stencil_step_batched_noalloc": (I, [I, I, ctypes.POINTER(StencilBatchItem), PO, VP]),
     "stencil_graph_capture_steps": (I, [I, I, PF, PF, PF, PF, PI64, D, D, PO, VP, ctypes.POINTER(VP)]),
     "stencil_graph_launch": (I, [VP, VP]),
     "stencil_graph_destroy": (I, [VP]),

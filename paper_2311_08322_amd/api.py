@@ -267,6 +267,12 @@ def stencil_step_batched(dtype, items, ws, opts=None, stream=None):
                                                _stream(stream)))
 
 
+def stencil_step_batched_noalloc(dtype, items, opts=None, stream=None):
+    arr = _batch_items(items)
+    _lib.check(_lib.lib().stencil_step_batched_noalloc(_dt(dtype), len(items), arr, _opts(opts),
+                                                       _stream(stream)))
+
+
 def stencil_step_adjoint_batched(dtype, items, ws, opts=None, stream=None):
     arr = _batch_adj_items(items)
     nb = 0 if ws is None else ws.numel() * ws.element_size()

@@ -52,7 +52,8 @@ def _units():
         u.append(("k_batched.hip", f"batched_{t}",
                   [f"-DGT4MI_T={t}", *(["-DGT4MI_UPLOAD"] if t == "float" else ["-DGT4MI_BATCHED_LONG"]),
                    *UNROLL]))
-    for src in ("k_adjoint.hip", "k_halo.hip", "k_hdiff.hip", "k_param.hip", "k_plain.hip", "k_step.hip", "api.cpp", "tune.cpp",
+    for src in ("k_adjoint.hip", "k_halo.hip", "k_hdiff.hip", "k_param.hip", "k_plain.hip", "k_step.hip", "noalloc.hip",
+                "api.cpp", "tune.cpp",
                 "graph.cpp", "batched.cpp", "param.cpp"):
         u.append((src, os.path.splitext(src)[0], []))
     return u

@@ -75,6 +75,19 @@ AdjArgs<T> adj_args(const stencil_field* xbar, const stencil_field* w, T* lam, i
                     int64_t l_sk, stencil_field* ubar, const int64_t* dom, double coeff,
                     double dt_dz, const void* mask);
 
+// persistent batched forward (batched.cpp).  ItemSpans: the buffers one
+// item reads and writes.  check_step_batch validates the arguments and
+// every item (not the workspace); launch_step_batch runs a validated,
+// non-empty batch with its work list in ws (at least
+// stencil_batch_workspace_bytes, 256-byte aligned, device memory).
+struct ItemSpans {
+  std::vector<Span> rd, wr;
+};
+int check_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, const stencil_options* opts,
+                     std::vector<ItemSpans>& spans);
+int launch_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
+                      const stencil_options* opts, hipStream_t stream);
+
 // tuning table (tune.cpp): tile and column store for (dtype, op, size class)
 void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* tile_i, int32_t* tile_j,
                 int32_t* column_store);

@@ -71,11 +71,6 @@ int check_batch_args(stencil_dtype dtype, int n, const void* items, const stenci
   return STENCIL_OK;
 }
 
-// The spans one item reads and writes.
-struct ItemSpans {
-  std::vector<Span> rd, wr;
-};
-
 // Writes of one item against every buffer of every other item.
 int check_cross_alias(const std::vector<ItemSpans>& sp) {
   const size_t n = sp.size();
@@ -374,6 +369,20 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
 }
 
 }  // namespace
+
+int check_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, const stencil_options* opts,
+                     std::vector<ItemSpans>& spans) {
+  TRY(check_batch_args(dtype, n, items, opts));
+  return check_forward_items(dtype, n, items, spans);
+}
+
+int launch_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
+                      const stencil_options* opts, hipStream_t stream) {
+  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP, n, items);
+  return dtype == STENCIL_F64 ? run_step_batched<double>(n, items, ws, ti, stream)
+                              : run_step_batched<float>(n, items, ws, ti, stream);
+}
+
 }  // namespace gt4mi
 
 using namespace gt4mi;
@@ -397,15 +406,13 @@ size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n, const s
 
 int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws, size_t ws_bytes,
                          const stencil_options* opts, hipStream_t stream) {
-  TRY(check_batch_args(dtype, n, items, opts));
   std::vector<ItemSpans> sp;
-  TRY(check_forward_items(dtype, n, items, sp));
-  TRY(check_workspace(ws, ws_bytes, stencil_batch_workspace_bytes(dtype, n, items), sp));
-  if (stencil_batch_workspace_bytes(dtype, n, items) == 0) return ok();
+  TRY(check_step_batch(dtype, n, items, opts, sp));
+  const size_t need = stencil_batch_workspace_bytes(dtype, n, items);
+  TRY(check_workspace(ws, ws_bytes, need, sp));
+  if (need == 0) return ok();
   TRY(check_device());
-  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP, n, items);
-  return dtype == STENCIL_F64 ? run_step_batched<double>(n, items, ws, ti, stream)
-                              : run_step_batched<float>(n, items, ws, ti, stream);
+  return launch_step_batch(dtype, n, items, ws, opts, stream);
 }
 
 int stencil_step_adjoint_batched(stencil_dtype dtype, int n, const stencil_batch_adjoint_item* items, void* ws,

@@ -348,6 +348,41 @@ def test_batch_validation(L):
     assert L.stencil_step_batched(1, 0, None, None, 0, None, None) == 0
 
 
+def test_batch_noalloc_validation(L):
+    """The no-allocation batch validates as stencil_step_batched does and
+    refuses a work list larger than its fixed array before any device work."""
+    m = re.search(r"#define\s+STENCIL_NOALLOC_SCRATCH_BYTES\s+(\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == _lib.NOALLOC_SCRATCH_BYTES
+    run = lambda arr, n=2, o=None: L.stencil_step_batched_noalloc(  # noqa: E731
+        1, n, arr, ctypes.byref(o) if o else None, None)
+    items = batch_items([(16, 12, 8), (20, 9, 30)])
+    assert run(items, n=-1) == code("STENCIL_E_ARG")
+    assert run(None, n=2) == code("STENCIL_E_NULL")
+    o = _lib.StencilOptions()
+    o.impl = _lib.IMPL_PLAIN
+    assert run(items, o=o) == code("STENCIL_E_UNSUPPORTED")
+    bad = batch_items([(16, 12, 8), (20, 9, 30)])
+    bad[1].out.data = bad[0].u.data
+    assert run(bad) == code("STENCIL_E_ALIAS")
+    long = batch_items([(16, 12, 8), (8, 8, 145)])
+    assert run(long) == code("STENCIL_E_UNSUPPORTED")
+    # any batch of up to 256 fields fits the array (both FP64 column groups
+    # present, the worst case of the table layout) ...
+    sizes = [(16, 12, 8 if n % 2 else 120) for n in range(256)]
+    many = batch_items(sizes)
+    for dt in (_lib.F32, _lib.F64):
+        assert 0 < L.stencil_batch_workspace_bytes(dt, 256, many) <= _lib.NOALLOC_SCRATCH_BYTES
+    # ... and a longer one is refused, naming the limit
+    more = batch_items([(16, 12, 8)] * 300)
+    assert L.stencil_batch_workspace_bytes(1, 300, more) > _lib.NOALLOC_SCRATCH_BYTES
+    assert run(more, n=300) == code("STENCIL_E_UNSUPPORTED")
+    assert str(_lib.NOALLOC_SCRATCH_BYTES) in _lib.last_error()
+    # no work: a no-op without a device
+    empty = batch_items([(0, 12, 8), (20, 9, 0)])
+    assert run(empty) == 0
+    assert L.stencil_step_batched_noalloc(1, 0, None, None, None) == 0
+
+
 def test_batch_adjoint_workspace_and_validation(L):
     fw = batch_items([(16, 12, 8), (20, 9, 30)])
     arr = (_lib.StencilBatchAdjointItem * 2)()
