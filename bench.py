@@ -106,45 +106,149 @@ def copy_bandwidth(mib: int, reps: int) -> dict:
     return {"copy_mib": mib, "bytes_per_copy": 2 * n * 8, "s_per_copy": t, "gbs": round(2 * n * 8 / t / 1e9, 1)}
 
 
-def bench_batched(api, fields, inputs, time_eager) -> dict:
-    """The 32-field uneven workload (FP64): one persistent launch against 32
-    separate fused launches and 32 plain per-stage chains."""
+def bench_batched(api, fields, inputs, time_eager, dtype) -> dict:
+    """The 32-field uneven workload: the forward step as one persistent
+    launch against 32 separate fused launches (and, in FP64, 32 plain
+    per-stage chains), and the step adjoint of the batch (with data_bar)
+    against 32 separate adjoint calls."""
     import torch
 
     dev = "cuda:0"
-    items, pts, byts = [], 0, 0
+    es = 8 if dtype == torch.float64 else 4
+    items, adj, pts, byts, abyts = [], [], 0, 0, 0
     for ni, nj, nk, f in inputs.batch_fields():
         dims = (ni, nj, nk)
-        items.append(dict(u=fields.from_padded(f.u, torch.float64, dev),
-                          data=fields.from_interior(f.data, torch.float64, dev),
-                          w=fields.from_interior(f.w, torch.float64, dev),
-                          out=fields.alloc(ni, nj, nk, torch.float64, dev, fill=0.0),
-                          domain=dims, coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, mask=None))
+        it = dict(u=fields.from_padded(f.u, dtype, dev), data=fields.from_interior(f.data, dtype, dev),
+                  w=fields.from_interior(f.w, dtype, dev), out=fields.alloc(ni, nj, nk, dtype, dev, fill=0.0),
+                  domain=dims, coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, mask=None)
+        items.append(it)
+        adj.append(dict(x_bar=fields.from_interior(inputs.cotangent(ni, nj, nk), dtype, dev), w=it["w"],
+                        u_bar=fields.alloc(ni, nj, nk, dtype, dev, fill=0.0),
+                        data_bar=fields.alloc(ni, nj, nk, dtype, dev, halo=0, fill=0.0), domain=dims,
+                        coeff=inputs.COEFF, dt_dz=inputs.DT_DZ, mask=fields.mask_tensor(dims, dev)))
         pts += ni * nj * nk
-        byts += step_bytes(ni, nj, nk, 8)
-    n = api.stencil_batch_workspace_bytes(api.F64, items)
-    ws = torch.empty(n, dtype=torch.uint8, device=dev)
-    t_batch = time_eager(lambda: api.stencil_step_batched(api.F64, items, ws), reps=10)
+        byts += step_bytes(ni, nj, nk, es)
+        abyts += adjoint_bytes(ni, nj, nk, es)
+    ws = torch.empty(api.stencil_batch_workspace_bytes(dtype, items), dtype=torch.uint8, device=dev)
+    t_batch = time_eager(lambda: api.stencil_step_batched(dtype, items, ws), reps=10)
 
     def separate():
         for it in items:
             api.stencil_step(it["u"], it["data"], it["w"], it["out"], it["domain"], inputs.COEFF, inputs.DT_DZ)
 
     t_sep = time_eager(separate, reps=10)
-    po = api.Options(impl=api.IMPL_PLAIN)
-    po.workspace = torch.empty(max(api.stencil_workspace_bytes(api.OP_STEP, api.F64, it["domain"], po)
-                                   for it in items), dtype=torch.uint8, device=dev)
+    res = {"fields": len(items), "points": pts, "dtype": "f64" if es == 8 else "f32",
+           "persistent_ms": round(t_batch * 1e3, 4), "separate_ms": round(t_sep * 1e3, 4),
+           "points_per_s": round(pts / t_batch, 1), "gbs": round(byts / t_batch / 1e9, 1),
+           "frac": round(byts / t_batch / 1e9 / PEAK_GBS, 4)}
+    if es == 8:
+        po = api.Options(impl=api.IMPL_PLAIN)
+        po.workspace = torch.empty(max(api.stencil_workspace_bytes(api.OP_STEP, api.F64, it["domain"], po)
+                                       for it in items), dtype=torch.uint8, device=dev)
 
-    def plain():
-        for it in items:
-            api.stencil_step(it["u"], it["data"], it["w"], it["out"], it["domain"], inputs.COEFF, inputs.DT_DZ,
-                             opts=po)
+        def plain():
+            for it in items:
+                api.stencil_step(it["u"], it["data"], it["w"], it["out"], it["domain"], inputs.COEFF,
+                                 inputs.DT_DZ, opts=po)
 
-    t_plain = time_eager(plain, reps=3)
-    return {"fields": len(items), "points": pts, "dtype": "f64",
-            "persistent_ms": round(t_batch * 1e3, 4), "separate_ms": round(t_sep * 1e3, 4),
-            "plain_ms": round(t_plain * 1e3, 4), "points_per_s": round(pts / t_batch, 1),
-            "gbs": round(byts / t_batch / 1e9, 1), "frac": round(byts / t_batch / 1e9 / PEAK_GBS, 4)}
+        res["plain_ms"] = round(time_eager(plain, reps=3) * 1e3, 4)
+    # the forward saving its masks, then the adjoint of the batch on them
+    for it, a in zip(items, adj):
+        it["mask"] = a["mask"]
+    t_mask = time_eager(lambda: api.stencil_step_batched(dtype, items, ws), reps=10)
+    res["persistent_mask_ms"] = round(t_mask * 1e3, 4)
+    torch.cuda.synchronize()
+    aws = torch.empty(api.stencil_batch_adjoint_workspace_bytes(dtype, adj), dtype=torch.uint8, device=dev)
+    t_adj = time_eager(lambda: api.stencil_step_adjoint_batched(dtype, adj, aws), reps=10)
+
+    def separate_adj():
+        for a in adj:
+            api.stencil_step_adjoint(a["x_bar"], a["w"], a["mask"], a["u_bar"], a["data_bar"], a["domain"],
+                                     inputs.COEFF, inputs.DT_DZ)
+
+    t_adj_sep = time_eager(separate_adj, reps=10)
+    res["adjoint"] = {"persistent_ms": round(t_adj * 1e3, 4), "separate_ms": round(t_adj_sep * 1e3, 4),
+                      "gbs": round(abyts / t_adj / 1e9, 1), "frac": round(abyts / t_adj / 1e9 / PEAK_GBS, 4),
+                      "ratio_adj_over_fwd_mask": round(t_adj / t_mask, 3)}
+    return res
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inputs, f512, adj32) -> dict:
+    """The CPU oracle (plain FP64 C loops) timed on the host: one step of
+    the 256x256x80 and 512x512x80 workloads and one step adjoint of the
+    256x256x80 workload, each single-threaded and with OpenMP on every
+    thread the process may use, median of 3 runs.  `value` is the all-cores
+    512x512x80 step rate.  With adj32 (the GPU's FP32 adjoint of the
+    256x256x80 workload and its forward mask), the oracle's adjoint on the
+    same binary32-rounded inputs and mask also gives that result's error."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from tests.helpers import rel_err, round_f32, unpack_mask
+
+    print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+    f256 = inputs.fields_for(inputs.STEP_256)
+    w4 = inputs.ADJ_256
+    f4 = inputs.fields_for(w4)
+    ob4 = inputs.cotangent(w4.ni, w4.nj, w4.nk)
+    mx4, my4 = orc.hdiff_masks(f4.u)
+    C, R = inputs.COEFF, inputs.DT_DZ
+    work = [("step 256x256x80", 256 * 256 * 80, lambda: orc.step(f256.u, f256.data, f256.w, C, R)),
+            ("step 512x512x80", 512 * 512 * 80, lambda: orc.step(f512.u, f512.data, f512.w, C, R)),
+            ("step adjoint 256x256x80", 256 * 256 * 80, lambda: orc.step_adjoint(ob4, f4.w, mx4, my4, C, R))]
+
+    def med3(fn):
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[1]
+
+    legs, t_total = [], time.perf_counter()
+    threads = 1
+    for mode in ("single", "openmp"):
+        for name, pts, fn in work:
+            if mode == "openmp":
+                with orc.threaded():
+                    threads = orc.threads()
+                    t = med3(fn)
+            else:
+                t = med3(fn)
+            legs.append({"workload": name, "threads": 1 if mode == "single" else threads,
+                         "ms": round(t * 1e3, 2), "points_per_s": round(pts / t, 1)})
+    head = [g for g in legs if g["workload"] == "step 512x512x80" and g["threads"] == threads][-1]
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    res = {"value": head["points_per_s"], "unit": "grid points/s", "cores": threads, "kind": "oracle",
+           "sample": "median of 3 runs of one FP64 step of the 512x512x80 workload on every host thread "
+                     "(OpenMP over independent levels and columns); the legs below time the 256x256x80 "
+                     "step and step adjoint and the single-threaded runs too",
+           "nproc": os.cpu_count(), "affinity": affinity, "cpu_model": cpu_model(), "legs": legs,
+           "wall_s": round(time.perf_counter() - t_total, 1)}
+    if adj32 is not None:
+        d4 = (w4.ni, w4.nj, w4.nk)
+        gx, gy = unpack_mask(adj32["mask"], *d4)
+        with orc.threaded():
+            ubr, dbr = orc.step_adjoint(round_f32(ob4), round_f32(f4.w), gx, gy, float(np.float32(C)), R)
+        res["fp32_adjoint_256_rel_err"] = {"u_bar": rel_err(adj32["ub"], ubr), "data_bar": rel_err(adj32["db"], dbr),
+                                           "what": "GPU FP32 step adjoint at 256x256x80 vs the FP64 oracle on "
+                                                   "the binary32-rounded cotangent and w with the GPU's FP32 mask "
+                                                   "(relative inf-norm error per output)"}
+    return res
 
 
 def main():
@@ -185,6 +289,7 @@ def main():
     f = inputs.fields_for(wl)
     K, W = args.steps, args.warmup
     out = {}
+    adj32 = None
 
     def mkfields(dtype):
         u_a = fields.from_padded(f.u, dtype, dev)
@@ -338,44 +443,58 @@ def main():
                           "adj_frac": round(ab / t_adj / 1e9 / PEAK_GBS, 4),
                           "fwd_mask_gbs": round(step_bytes(ni, nj, nk, 8, True) / t_fwd / 1e9, 1)}
         # ---------------------------- the adjoint workload 256x256x80, rotating sets
-        # one set (about 170 MB) fits the 256 MB last-level cache, so R sets
-        # (> 512 MB together) are cycled and each call touches a cold set
-        print("bench: adjoint vs forward at 256x256x80 (rotating buffer sets)", file=sys.stderr, flush=True)
+        # one set (about 170 MB in FP64) fits the 256 MB last-level cache, so
+        # R sets (> 512 MB together in FP64) are cycled and each call touches
+        # a cold set
         w4 = inputs.ADJ_256
         d4 = (w4.ni, w4.nj, w4.nk)
         f4 = inputs.fields_for(w4)
         ob4 = inputs.cotangent(*d4)
-        sets = []
-        for _ in range(4):
-            sets.append(dict(u=fields.from_padded(f4.u, torch.float64, dev),
-                             data=fields.from_interior(f4.data, torch.float64, dev),
-                             w=fields.from_interior(f4.w, torch.float64, dev),
-                             out=fields.alloc(*d4, torch.float64, dev, halo=0, fill=0.0),
-                             mask=fields.mask_tensor(d4, dev),
-                             xb=fields.from_interior(ob4, torch.float64, dev),
-                             ub=fields.alloc(*d4, torch.float64, dev, fill=0.0),
-                             db=fields.alloc(*d4, torch.float64, dev, halo=0, fill=0.0)))
-        rot = {"n": 0}
+        for dtype, key, nsets in ((torch.float64, "adjoint_256", 4), (torch.float32, "adjoint_256_f32", 8)):
+            print(f"bench: adjoint vs forward at 256x256x80 {key} (rotating buffer sets)", file=sys.stderr,
+                  flush=True)
+            sets = []
+            for _ in range(nsets):
+                sets.append(dict(u=fields.from_padded(f4.u, dtype, dev),
+                                 data=fields.from_interior(f4.data, dtype, dev),
+                                 w=fields.from_interior(f4.w, dtype, dev),
+                                 out=fields.alloc(*d4, dtype, dev, halo=0, fill=0.0),
+                                 mask=fields.mask_tensor(d4, dev),
+                                 xb=fields.from_interior(ob4, dtype, dev),
+                                 ub=fields.alloc(*d4, dtype, dev, fill=0.0),
+                                 db=fields.alloc(*d4, dtype, dev, halo=0, fill=0.0)))
+            rot = {"n": 0}
 
-        def fwd4():
-            z = sets[rot["n"] % len(sets)]
-            rot["n"] += 1
-            api.stencil_step(z["u"], z["data"], z["w"], z["out"], d4, inputs.COEFF, inputs.DT_DZ, mask=z["mask"])
+            def fwd4():
+                z = sets[rot["n"] % len(sets)]
+                rot["n"] += 1
+                api.stencil_step(z["u"], z["data"], z["w"], z["out"], d4, inputs.COEFF, inputs.DT_DZ,
+                                 mask=z["mask"])
 
-        def adj4():
-            z = sets[rot["n"] % len(sets)]
-            rot["n"] += 1
-            api.stencil_step_adjoint(z["xb"], z["w"], z["mask"], z["ub"], z["db"], d4, inputs.COEFF, inputs.DT_DZ)
+            def adj4():
+                z = sets[rot["n"] % len(sets)]
+                rot["n"] += 1
+                api.stencil_step_adjoint(z["xb"], z["w"], z["mask"], z["ub"], z["db"], d4, inputs.COEFF,
+                                         inputs.DT_DZ)
 
-        t_f4 = time_eager(fwd4, reps=40)
-        t_a4 = time_eager(adj4, reps=40)
-        ab4 = adjoint_bytes(*d4, 8)
-        out["adjoint_256"] = {"ratio_adj_over_fwd": round(t_a4 / t_f4, 3), "fwd_mask_ms": round(t_f4 * 1e3, 4),
-                              "adj_ms": round(t_a4 * 1e3, 4), "adj_gbs": round(ab4 / t_a4 / 1e9, 1),
-                              "adj_frac": round(ab4 / t_a4 / 1e9 / PEAK_GBS, 4),
-                              "what": "step adjoint (with data_bar) vs forward step saving the mask, "
-                                      "256x256x80 FP64, 4 rotating buffer sets of ~170 MB"}
-        del sets
+            t_f4 = time_eager(fwd4, reps=40)
+            t_a4 = time_eager(adj4, reps=40)
+            es = 8 if dtype == torch.float64 else 4
+            ab4 = adjoint_bytes(*d4, es)
+            out[key] = {"ratio_adj_over_fwd": round(t_a4 / t_f4, 3), "fwd_mask_ms": round(t_f4 * 1e3, 4),
+                        "adj_ms": round(t_a4 * 1e3, 4), "adj_gbs": round(ab4 / t_a4 / 1e9, 1),
+                        "adj_frac": round(ab4 / t_a4 / 1e9 / PEAK_GBS, 4),
+                        "what": f"step adjoint (with data_bar) vs forward step saving the mask, 256x256x80 "
+                                f"{'FP64' if es == 8 else 'FP32'}, {nsets} rotating buffer sets of "
+                                f"~{round(ab4 / 1e6)} MB"}
+            if dtype == torch.float32:
+                # the outputs of set 0 (forward mask, u_bar, data_bar) for the
+                # error statement the CPU leg makes from its own adjoint run
+                z = sets[0]
+                torch.cuda.synchronize()
+                adj32 = dict(mask=z["mask"].cpu(), ub=fields.padded(z["ub"], *d4).cpu().numpy(),
+                             db=fields.interior(z["db"], *d4).cpu().numpy())
+            del sets
         # ------------------------------------------------ plain per-stage chain
         print("bench: plain per-stage kernels", file=sys.stderr, flush=True)
         po = api.Options(impl=api.IMPL_PLAIN)
@@ -419,7 +538,8 @@ def main():
     # ------------------------------------------------ batched uneven fields
     if not args.only_step:
         print("bench: 32 uneven fields, persistent launch vs separate launches", file=sys.stderr, flush=True)
-        out["batched"] = bench_batched(api, fields, inputs, time_eager)
+        out["batched"] = bench_batched(api, fields, inputs, time_eager, torch.float64)
+        out["batched_f32"] = bench_batched(api, fields, inputs, time_eager, torch.float32)
 
     # ------------------------------------------------------ achievable bandwidth
     if not args.only_step:
@@ -432,18 +552,7 @@ def main():
 
     # -------------------------------------------------------------- CPU baseline
     if not args.no_cpu:
-        from oracle import oracle as orc
-
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        nrep, t0 = 0, time.perf_counter()
-        while nrep < 5 and time.perf_counter() - t0 < 20.0:
-            orc.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ)
-            nrep += 1
-        tc = (time.perf_counter() - t0) / nrep
-        out["cpu_baseline"] = {"value": round(npts / tc, 1), "unit": "grid points/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{nrep} full FP64 steps of the 512x512x80 workload, single-threaded C "
-                                         f"loops (gcc -O2), {tc:.2f} s/step"}
+        out["cpu_baseline"] = cpu_baseline(inputs, f, adj32 if not args.only_step else None)
     print(json.dumps(out), flush=True)
 
 
