@@ -163,6 +163,16 @@ struct LevelCursor {
   __device__ __forceinline__ void advance(bool go) { p += go ? step : 0; }
 };
 
+// ------------------------------------------------------------ prefetch
+// Pins the loads issued before it to this point of the program.  The column
+// kernels unroll their level loop with a uniform exit after every step, and
+// the compiler otherwise sinks each prefetched load into the step that
+// consumes it (the exits make the load look wasted on the paths that leave
+// early), so the prefetch degenerates into a load followed by a full wait.
+// An empty asm that clobbers memory keeps the loads where they are written
+// without forcing a wait for them.
+__device__ __forceinline__ void pin_prefetch() { __asm__ volatile("" ::: "memory"); }
+
 // ------------------------------------------------------------ limiter
 // The flux is zeroed where flux * gradient > 0 (the workload's definition
 // of the diffusion named in Sec. 3.1), the product taken literally in the working precision.

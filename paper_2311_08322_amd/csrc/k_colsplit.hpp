@@ -74,6 +74,7 @@ __device__ __forceinline__ void column_split_tile(const StepArgs<T>& A, int tile
     const int slot = s % PD;
     const T rhs = pr[slot], wn = pw[slot];
     if (s + PD < NKH) issue(slot, s + PD);
+    pin_prefetch();
     const bool act = s < nlev;
     const int k = k0 + dir * s;
     const T nr = (s > 0) ? sn * wp : T(0);

@@ -247,6 +247,7 @@ __global__ void __launch_bounds__(TI* TJ) k_step_fused(StepArgs<T> A) {
       for (int q = 0; q < NLD; ++q) U[tid + q * NT] = pu[s][q];
       const T dk = pd[s], wk1 = pw[s];
       if (k + PD < nk) issue(s, k + PD);
+      pin_prefetch();
       __syncthreads();
       bool kxr, kxl, kyr, kyl;
       const T h = hdiff_diamond<T, HI>(U + cu, coeff, kxr, kxl, kyr, kyl);
@@ -321,6 +322,7 @@ __global__ void __launch_bounds__(kWG) k_vadv_fused(StepArgs<T> A) {
       const int s = k % PD;
       const T dk = pu[s] + pd[s], wk1 = pw[s];
       if (k + PD < nk) issue(s, k + PD);
+      pin_prefetch();
       const T a = (k > 0) ? -r4 * wk : T(0);
       const T c = (k < nk - 1) ? r4 * wk1 : T(0);
       const T b = T(1) + absv(a) + absv(c);

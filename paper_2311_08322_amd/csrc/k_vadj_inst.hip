@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(kWG) k_vadv_adjoint_fused(AdjArgs<T> A) {
       const int s = k % PD;
       const T xb = px[s], wk1 = pw[s];
       if (k + PD < nk) issue(s, k + PD);
+      pin_prefetch();
       const T a = (k > 0) ? -r4 * wk : T(0);
       const T c = (k < nk - 1) ? r4 * wk1 : T(0);
       const T b = T(1) + absa(a) + absa(c);
