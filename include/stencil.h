@@ -343,9 +343,9 @@ size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
 int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
                          size_t ws_bytes, const stencil_options* opts, hipStream_t stream);
 /* The adjoints of a batch: one persistent launch for the column adjoints
- * (work items: field, 64x4 column tile), one for the horizontal gathers
- * (work items: field, four 60x16 strips of the padded domain, block of
- * levels).  ws as for the forward, sized by
+ * (work items: field, 64x4 column tile), then one launch for the horizontal
+ * gathers with a workgroup per work item (field, four 60x16 strips of the
+ * padded domain, level).  ws as for the forward, sized by
  * stencil_batch_adjoint_workspace_bytes; opts->tile_i is not used. */
 int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
                                  const stencil_batch_adjoint_item* items, void* ws,

@@ -24,8 +24,8 @@ constexpr int kWsAlign = 256;
 
 int64_t r256(int64_t b) { return MaskLayout::round256(b); }
 
-// bytes of one table: header, prefix[n + 1], kper[n], then n argument blocks
-int64_t table_head_bytes(int n) { return r256((int64_t)sizeof(BatchHeader) + 4 * (2 * (int64_t)n + 1)); }
+// bytes of one table: header and prefix[n + 1], then n argument blocks
+int64_t table_head_bytes(int n) { return r256((int64_t)sizeof(BatchHeader) + 4 * ((int64_t)n + 1)); }
 int64_t table_bytes(int n, size_t arg_bytes) { return table_head_bytes(n) + r256((int64_t)n * (int64_t)arg_bytes); }
 
 size_t arg_bytes(stencil_dtype dt, bool adj) {
@@ -180,10 +180,10 @@ std::vector<int> lpt_order(int n, const Item* it, bool (*has_work)(const int64_t
 bool interior_work(const int64_t* d) { return !domain_empty(d); }
 bool halo_work(const int64_t* d) { return d[2] > 0; }
 
-// Writes one table (header, prefix, kper, argument blocks) into blob at off.
+// Writes one table (header, prefix, argument blocks) into blob at off.
 template <typename Args>
 int32_t write_table(std::vector<uint8_t>& blob, size_t off, const std::vector<Args>& args,
-                    const std::vector<int32_t>& items, const std::vector<int32_t>& kper) {
+                    const std::vector<int32_t>& items) {
   const int n = (int)args.size();
   BatchHeader h;
   memset(&h, 0, sizeof h);
@@ -194,21 +194,22 @@ int32_t write_table(std::vector<uint8_t>& blob, size_t off, const std::vector<Ar
   uint8_t* p = blob.data() + off;
   memcpy(p, &h, sizeof h);
   memcpy(p + sizeof h, prefix.data(), 4 * (n + 1));
-  if (!kper.empty()) memcpy(p + sizeof h + 4 * (n + 1), kper.data(), 4 * n);
   if (n) memcpy(p + table_head_bytes(n), args.data(), n * sizeof(Args));
   return h.total;
 }
 
 // ---------------------------------------------------------------- forward
-// FP64 fields whose columns exceed kBatchedShortNkF64 levels run in a launch
-// of their own (128-column tiles, e and f in VGPRs); the rest share one launch.
-bool long_fp64(stencil_dtype dt, const int64_t* d) { return dt == STENCIL_F64 && d[2] > kBatchedShortNkF64; }
+// FP64 fields whose columns exceed kBatchedShortNk levels run in a launch of
+// their own (128-column tiles, e and f in VGPRs); the rest share one launch
+// in the 40-level class.  FP32 fields all run in one launch (the 72-level
+// class): splitting them by class was measured slower.
+bool long_class(stencil_dtype dt, const int64_t* d) { return dt == STENCIL_F64 && d[2] > kBatchedShortNk; }
 
 // Table sizes of the forward batch: [short group, long group].
 void forward_groups(stencil_dtype dt, int n, const stencil_batch_item* it, int m[2]) {
   m[0] = m[1] = 0;
   for (int a = 0; a < n; ++a)
-    if (interior_work(it[a].domain)) ++m[long_fp64(dt, it[a].domain) ? 1 : 0];
+    if (interior_work(it[a].domain)) ++m[long_class(dt, it[a].domain) ? 1 : 0];
 }
 
 template <typename T>
@@ -220,14 +221,15 @@ int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, 
   int64_t off = 0;
   // the long group first: its columns are the longest (longest work first)
   for (int g = 1; g >= 0; --g) {
-    const int tile_j = (g ? kSplitLongNT : kWG) / tile_i;
+    const bool long_tiles = g == 1;  // FP64 long columns: 128-column tiles
+    const int tile_j = (long_tiles ? kSplitLongNT : kWG) / tile_i;
     std::vector<StepArgs<T>> args;
     std::vector<int32_t> items;
     bool any_mask = false;
     int64_t total = 0;
     for (int a : ord) {
       const stencil_batch_item& x = it[a];
-      if (long_fp64(dt, x.domain) != (g == 1)) continue;
+      if (long_class(dt, x.domain) != (g == 1)) continue;
       StepArgs<T> A = step_args<T>(&x.u, &x.data, &x.w, const_cast<stencil_field*>(&x.out), x.domain, x.coeff,
                                    x.dt_dz, x.mask);
       A.tiles_i = (A.ni + tile_i - 1) / tile_i;
@@ -241,12 +243,12 @@ int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, 
     if (m == 0) continue;
     if (total > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch of %lld tiles is too large", (long long)total);
     std::vector<uint8_t> blob((size_t)table_bytes(m, sizeof(StepArgs<T>)), 0);
-    write_table(blob, 0, args, items, {});
+    write_table(blob, 0, args, items);
     TRY(hip_status(launch_upload(base + off, blob.data(), blob.size(), s), "batched table upload"));
     BatchHeader* h = reinterpret_cast<BatchHeader*>(base + off);
     const auto* ent = reinterpret_cast<const StepArgs<T>*>(base + off + table_head_bytes(m));
-    if constexpr (sizeof(T) == 8) {  // only FP64 has a long group
-      if (g == 1) {
+    if constexpr (sizeof(T) == 8) {
+      if (long_tiles) {
         TRY(hip_status(launch_step_batched_long<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched, long)"));
         off += (int64_t)blob.size();
         continue;
@@ -322,7 +324,7 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
     vtotal += C.ntiles;
   }
 
-  // horizontal gathers: groups of strips over the padded domain, in blocks of levels
+  // horizontal gathers: groups of strips over the padded domain, one level per item
   std::vector<AdjArgs<T>> hargs(mh);
   for (int e = 0; e < mh; ++e) {
     const int a = hord[e];
@@ -335,28 +337,20 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
     A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);  // strips
     hargs[e] = A;
   }
-  // one level-block length for all fields: short enough for a few work items
-  // per resident workgroup
   auto groups = [](const AdjArgs<T>& A) { return (int64_t)(A.ntiles + kStripsPerWG - 1) / kStripsPerWG; };
-  int kper = 32;
-  auto count = [&](int kp) {
-    int64_t t = 0;
-    for (const auto& A : hargs) t += groups(A) * ((A.nk + kp - 1) / kp);
-    return t;
-  };
-  while (kper > 1 && count(kper) < 8192) kper /= 2;
-  std::vector<int32_t> hitems(mh), hkper(mh);
+  std::vector<int32_t> hitems(mh);
+  int64_t htotal = 0;
   for (int e = 0; e < mh; ++e) {
-    const int kp = std::min(kper, hargs[e].nk);
-    hkper[e] = kp;
-    hitems[e] = (int32_t)(groups(hargs[e]) * ((hargs[e].nk + kp - 1) / kp));
+    const int64_t c = groups(hargs[e]) * hargs[e].nk;
+    if (c > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
+    hitems[e] = (int32_t)c;
+    htotal += c;
   }
-  const int64_t htotal = count(kper);
   if (vtotal > INT32_MAX / 2 || htotal > INT32_MAX / 2) return fail(STENCIL_E_UNSUPPORTED, "batch too large");
 
   std::vector<uint8_t> blob((size_t)(vbytes + hbytes), 0);
-  write_table(blob, 0, vargs, vitems, {});
-  write_table(blob, (size_t)vbytes, hargs, hitems, hkper);
+  write_table(blob, 0, vargs, vitems);
+  write_table(blob, (size_t)vbytes, hargs, hitems);
   TRY(hip_status(launch_upload(ws, blob.data(), blob.size(), s), "batched table upload"));
   if (vtotal > 0) {
     BatchHeader* h = reinterpret_cast<BatchHeader*>(base);

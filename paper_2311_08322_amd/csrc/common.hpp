@@ -15,9 +15,6 @@ constexpr int kWG = 256;          // threads per workgroup of every tile kernel
 // kSplitLongNT-column tiles
 constexpr int kSplitRegNkF64 = 96;
 constexpr int kSplitLongNT = 128;
-// the batched forward's FP64 columns up to this many levels share one launch
-// of 256-column tiles; longer ones run in a launch of kSplitLongNT-column tiles
-constexpr int kBatchedShortNkF64 = 80;
 // the hdiff adjoint's strips: 64 lanes in i (60 outputs), kStripRows rows in j
 constexpr int kStripOut = 60;
 constexpr int kStripOut2 = 124;  // FP32: two columns per lane, 124 outputs

@@ -1,14 +1,16 @@
-// k_batched.hip -- persistent kernels that run a batch of fields of uneven
-// sizes in one launch each.
+// k_batched.hip -- kernels that run a batch of fields of uneven sizes in one
+// launch each.
 //
 // The host sorts the fields longest column first and writes a table into
 // the caller's workspace (a header with the per-field prefix sums of work
 // items, then one argument block per field) with small copy kernels, so the
 // whole call is stream-ordered device work that a HIP graph can capture.
-// Every workgroup of the persistent launch then pulls work items (field,
-// tile or strips[, level block]) from an atomic queue in the header until
-// the queue is exhausted.  A work item runs the same body as the
-// single-field kernel (the step's tile picked by the field's column length).
+// The column kernels (forward step, column adjoint) are persistent: every
+// workgroup pulls work items (field, column tile) from an atomic queue in
+// the header until the queue is exhausted.  The horizontal adjoint's items
+// (field, four strips, one level) are short, so it launches one workgroup
+// per item instead, which finds its item in the prefix sums.  A work item
+// runs the same body as the single-field kernel.
 #include <string.h>
 
 #include "common.hpp"
@@ -88,11 +90,11 @@ __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Forward step.  FP64: the host sends columns up to kBatchedShortNkF64
-// levels here (both halves' factors in VGPRs, the 40-level class; the
-// 48-level class spills beside the persistent loop's own registers) and the
-// longer ones to k_step_batched_long; FP32 keeps all up to 144 here.
-template <typename T, int TI, int TJ, bool MASK>
+// Forward step, half-column register class NKH.  FP64 columns up to
+// kBatchedShortNk levels run in the 40-level class (the 48-level class
+// would spill beside the persistent loop's own registers), longer ones in
+// k_step_batched_long; FP32 columns all run in the 72-level class.
+template <typename T, int TI, int TJ, int NKH, bool MASK>
 __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
   __shared__ SplitSmem<T, TI, TJ> sm;
   __shared__ int slot;
@@ -102,17 +104,13 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     const int e = find_entry(h, w);
     const StepArgs<T> A = uniform_ld(ent + e);
     const int tile = w - uniform_ld(h->prefix() + e);
-    if constexpr (sizeof(T) == 8) {
-      step_split_tile<T, TI, TJ, kBatchedShortNkF64 / 2, GT4MI_PD, MASK, 1>(A, tile, sm);
-    } else {
-      step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 1>(A, tile, sm);
-    }
+    step_split_tile<T, TI, TJ, NKH, GT4MI_PD, MASK, 1>(A, tile, sm);
     __syncthreads();  // the LDS is reused by the next item
   }
 }
 
 #ifdef GT4MI_BATCHED_LONG
-// FP64 columns of kBatchedShortNkF64+1 .. 144 levels: TI x (kSplitLongNT / TI)
+// FP64 columns of kBatchedShortNk+1 .. 144 levels: TI x (kSplitLongNT / TI)
 // tiles of 256 lanes with e and f in VGPRs, as the single-field long form.
 template <typename T, int TI, bool MASK>
 __global__ void __launch_bounds__(2 * kSplitLongNT) k_step_batched_long(BatchHeader* h, const StepArgs<T>* ent) {
@@ -154,46 +152,46 @@ __global__ void __launch_bounds__(2 * kWG) k_vadj_batched(BatchHeader* h, const 
   }
 }
 
-// Horizontal adjoint: work items (field, group of kStripsPerWG strips, level
-// block); each wave walks its strip of the group through the block's levels
-// (FP32 strips hold two columns per lane, as in the single-field gather).
+// Horizontal adjoint: one workgroup per work item (field, group of
+// kStripsPerWG strips, level), as the single-field gather's grid; each wave
+// walks its strip of the group (FP32 strips hold two columns per lane).
 template <typename T>
-__global__ void __launch_bounds__(kWG) k_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent) {
-  __shared__ int slot;
-  for (;;) {
-    const int w = next_work(h, &slot);
-    if (w < 0) break;
-    const int e = find_entry(h, w);
-    const AdjArgs<T> A = uniform_ld(ent + e);
-    const int local = w - uniform_ld(h->prefix() + e);
-    const int groups = (A.ntiles + kStripsPerWG - 1) / kStripsPerWG;
-    const int g = local % groups, kb = local / groups;
-    const int kper = uniform_ld(h->kper() + e);
-    const int t = __builtin_amdgcn_readfirstlane(g * kStripsPerWG + (int)(threadIdx.x >> 6));
-    if (t < A.ntiles) {
-      const int kend = min(kb * kper + kper, A.nk);
-      for (int k = kb * kper; k < kend; ++k) {
-        if constexpr (sizeof(T) == 4)
-          hdiff_adjoint_strip2<kStripRows, kStripPD, false>(A, t, k);  // two columns per lane
-        else
-          hdiff_adjoint_strip<T, kStripRows, kStripPD, false>(A, t, k);
-      }
-    }
+__global__ void __launch_bounds__(kWG) k_hadj_batched(const BatchHeader* h, const AdjArgs<T>* ent) {
+  const int w = blockIdx.x;
+  const int e = find_entry(h, w);
+  const AdjArgs<T> A = uniform_ld(ent + e);
+  const int local = w - uniform_ld(h->prefix() + e);
+  const int groups = (A.ntiles + kStripsPerWG - 1) / kStripsPerWG;
+  const int g = local % groups, k = local / groups;
+  const int t = __builtin_amdgcn_readfirstlane(g * kStripsPerWG + (int)(threadIdx.x >> 6));
+  if (t < A.ntiles) {
+    if constexpr (sizeof(T) == 4)
+      hdiff_adjoint_strip2<kStripRows, kStripPD, false>(A, t, k);  // two columns per lane
+    else
+      hdiff_adjoint_strip<T, kStripRows, kStripPD, false>(A, t, k);
   }
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename T>
-hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                               hipStream_t s) {
+template <typename T, int NKH>
+hipError_t launch_step_batched_class(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                                     hipStream_t s) {
   auto go = [&](auto kernel) {
     const int grid = persistent_grid(kernel, 2 * kWG, total);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(2 * kWG), 0, s, h, ent);
     return hipGetLastError();
   };
-  if (tile_i == 64) return mask ? go(k_step_batched<T, 64, 4, true>) : go(k_step_batched<T, 64, 4, false>);
-  if (tile_i == 32) return mask ? go(k_step_batched<T, 32, 8, true>) : go(k_step_batched<T, 32, 8, false>);
-  return mask ? go(k_step_batched<T, 16, 16, true>) : go(k_step_batched<T, 16, 16, false>);
+  if (tile_i == 64)
+    return mask ? go(k_step_batched<T, 64, 4, NKH, true>) : go(k_step_batched<T, 64, 4, NKH, false>);
+  if (tile_i == 32)
+    return mask ? go(k_step_batched<T, 32, 8, NKH, true>) : go(k_step_batched<T, 32, 8, NKH, false>);
+  return mask ? go(k_step_batched<T, 16, 16, NKH, true>) : go(k_step_batched<T, 16, 16, NKH, false>);
+}
+
+template <typename T>
+hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
+                               hipStream_t s) {
+  return launch_step_batched_class<T, sizeof(T) == 8 ? kBatchedShortNk / 2 : 72>(h, ent, total, tile_i, mask, s);
 }
 
 #ifdef GT4MI_BATCHED_LONG
@@ -220,8 +218,8 @@ hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total
 
 template <typename T>
 hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total, hipStream_t s) {
-  const int grid = persistent_grid(k_hadj_batched<T>, kWG, total);
-  hipLaunchKernelGGL(k_hadj_batched<T>, dim3(grid), dim3(kWG), 0, s, h, ent);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hadj_batched<T>, dim3(total), dim3(kWG), 0, s, h, ent);
   return hipGetLastError();
 }
 

@@ -99,13 +99,34 @@ __device__ __forceinline__ void column_split_tile(const StepArgs<T>& A, int tile
   const T xm = (fb - eb * ft) * recip(T(1) - eb * et);
   const T xm1 = ft - et * xm;
   T x = half ? xm1 : xm;
+  if constexpr (COL == 1) {
 #pragma unroll
-  for (int s = NKH - 1; s >= 0; --s) {
-    if (s < nlev) {
-      const auto ro = vo.at(k0 + dir * s);
-      if constexpr (COL == 1) x = fv[s] - ev[s] * x;
-      else x = buf_ld(ro, ooff, T()) - ev[s] * x;
-      buf_st(ro, ooff, x);
+    for (int s = NKH - 1; s >= 0; --s) {
+      if (s < nlev) {
+        const auto ro = vo.at(k0 + dir * s);
+        x = fv[s] - ev[s] * x;
+        buf_st(ro, ooff, x);
+      }
+    }
+  } else {
+    // The staged f comes back PDB levels ahead of its use.  The walk is
+    // branch-free so that the load counters stay exact: levels this half
+    // does not own read 0 and store nothing (offset outside the window), and
+    // leave x unchanged.  Level s's value is consumed before slot s % PDB is
+    // refilled with level s - PDB.
+    constexpr int PDB = 4;
+    T pf[PDB];
+    auto level = [&](int s) { return vo.at(min(max(k0 + dir * s, 0), nk - 1)); };
+#pragma unroll
+    for (int s = NKH - 1 + PDB; s >= 0; --s) {
+      if (s < NKH) {
+        const bool act = s < nlev;
+        const T xn = pf[s % PDB] - ev[s] * x;
+        x = act ? xn : x;
+        buf_st(level(s), act ? ooff : kOffNone, x);
+      }
+      const int sl = s - PDB;
+      if (sl >= 0) pf[sl % PDB] = buf_ld(level(sl), sl < nlev ? ooff : kOffNone, T());
     }
   }
 }

@@ -65,22 +65,25 @@ hipError_t launch_vadj_classes(const AdjArgs<T>& A, hipStream_t s);
 template <typename T>
 hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s);
 
-// persistent batched launches (k_batched.hip).  The work list sits in device
-// memory: a BatchHeader, then prefix[n + 1] (first work item of each field)
-// and kper[n] (levels per work item, horizontal adjoint only).
+// batched launches (k_batched.hip).  The work list sits in device memory: a
+// BatchHeader, then prefix[n + 1] (first work item of each field), then the
+// fields' argument blocks.
 struct BatchHeader {
-  uint32_t queue;  // next work item, taken with atomicAdd
+  uint32_t queue;  // next work item, taken with atomicAdd (persistent launches)
   int32_t n;       // fields
   int32_t total;   // work items
   int32_t pad;
   __host__ __device__ const int32_t* prefix() const { return reinterpret_cast<const int32_t*>(this + 1); }
-  __host__ __device__ const int32_t* kper() const { return prefix() + n + 1; }
 };
 // longest column of a batched field (both halves' e in VGPRs, f staged)
 constexpr int kMaxBatchedNk = 144;
 // stream-ordered copy of a small host table into device memory (kernel
 // arguments, so that a captured graph holds its own copy)
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+// FP64 columns of up to kBatchedShortNk levels run in the 40-level
+// half-column class, longer ones in launch_step_batched_long; FP32 columns
+// all run in the 72-level class.
+constexpr int kBatchedShortNk = 80;
 template <typename T>
 hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
                                hipStream_t s);
