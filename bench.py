@@ -298,9 +298,17 @@ def main():
         w = fields.from_interior(f.w, dtype, dev)
         return u_a, u_b, data, w
 
+    tuned = {}
+
     def time_graph(dtype, nsteps, reps):
         u_a, u_b, data, w = mkfields(dtype)
         s = torch.cuda.Stream()
+        # the library's autotuner picks tile, column store and tile order for
+        # this size class on the very buffers the graph will step (where the
+        # fields sit in memory matters as well as their shape)
+        print(f"bench: autotuning the fused step ({dtype}) on its fields", file=sys.stderr, flush=True)
+        api.stencil_autotune_fields(u_a, data, w, u_b, dims, reps=3, stream=s)
+        tuned["f64" if dtype == torch.float64 else "f32"] = api.stencil_tuning_lookup(dtype, api.OP_STEP, dims)
         for n in range(W):  # eager warm-up steps
             src, dst = (u_a, u_b) if n % 2 == 0 else (u_b, u_a)
             api.stencil_step(src, data, w, dst, dims, inputs.COEFF, inputs.DT_DZ, stream=s)
@@ -354,14 +362,6 @@ def main():
             ts.append(e0.elapsed_time(e1) / 1e3 / reps)
         return sorted(ts)[len(ts) // 2]
 
-    # ------------------------------------------------------------ autotuning
-    # the library's autotuner picks tile and column store for this size class
-    print("bench: autotuning the fused step", file=sys.stderr, flush=True)
-    tuned = {}
-    for dt, name in ((api.F64, "f64"), (api.F32, "f32")):
-        api.stencil_autotune(dt, api.OP_STEP, dims, reps=3)
-        tuned[name] = api.stencil_tuning_lookup(dt, api.OP_STEP, dims)
-
     # ---------------------------------------------------------------- FP64 step
     print(f"bench: fused step {dims} fp64, {K} steps per graph, {args.reps} replays", file=sys.stderr,
           flush=True)
@@ -369,7 +369,7 @@ def main():
     t_step = t_ev / K
     b64 = step_bytes(ni, nj, nk, 8)
     gbs = b64 / t_step / 1e9
-    ti, tj, col = tuned["f64"]
+    ti, tj, col, _ = tuned["f64"]
     nkh = nk - nk // 2
     kname = (f"k_step_split<double, {ti}, {tj}, {split_class(nkh)}, 2, false, {1 if nk <= 80 else 2}, false>"
              if col == api.COLUMN_SPLIT else f"k_step_fused<double, {ti}, {tj}, 80, 2, {col}>")
@@ -393,7 +393,7 @@ def main():
         "config": {"workload": "fused hdiff+vadv step 512x512x80, halo 2, hipGraph of K steps",
                    "ni": ni, "nj": nj, "nk": nk, "graph_steps": K, "wall_s_per_graph": round(t_wall, 6),
                    "tuned_tile_f64": f"{tuned['f64'][0]}x{tuned['f64'][1]}", "column_store_f64": tuned["f64"][2],
-                   "tuned_tile_f32": f"{tuned['f32'][0]}x{tuned['f32'][1]}", "column_store_f32": tuned["f32"][2]},
+                   "tile_order_f64": tuned["f64"][3]},
         "roofline": roof,
     })
 
@@ -403,9 +403,10 @@ def main():
         # replays, and every tile the tuner may pick gets measured
         u_a, u_b, data, w = mkfields(torch.float64)
         for tile in (64, 32, 16):
-            o = api.Options(tile_i=tile, tile_j=256 // tile, column_store=api.COLUMN_SPLIT)
-            for n in range(3):
-                api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
+            for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
+                o = api.Options(tile_i=tile, tile_j=256 // tile, column_store=api.COLUMN_SPLIT, tile_order=order)
+                for n in range(3):
+                    api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
         if args.with_adjoint:
             # the step adjoint (column adjoint + gather) on the forward's mask
             mask = fields.mask_tensor(dims, dev)
@@ -422,6 +423,8 @@ def main():
         # ------------------------------------------------------------ FP32 step
         print("bench: fused step fp32", file=sys.stderr, flush=True)
         t32, _ = time_graph(torch.float32, K, args.reps)
+        out["config"].update({"tuned_tile_f32": f"{tuned['f32'][0]}x{tuned['f32'][1]}",
+                              "column_store_f32": tuned["f32"][2], "tile_order_f32": tuned["f32"][3]})
         b32 = step_bytes(ni, nj, nk, 4)
         out["fp32"] = {"value": round(npts * K / t32, 1), "unit": "grid points/s",
                        "ms_per_step": round(t32 / K * 1e3, 4), "gbs": round(b32 / (t32 / K) / 1e9, 1),

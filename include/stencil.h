@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define STENCIL_ABI_VERSION 2
+#define STENCIL_ABI_VERSION 3
 #define STENCIL_HALO 2
 
 typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype;
@@ -114,6 +114,18 @@ typedef enum {
                                    (i mod ni, j mod nj), corners included */
 } stencil_boundary;
 
+/* Order in which the fused step's workgroups take their column tiles.  The
+ * dispatcher hands consecutive workgroups to the 8 XCDs in turn, each with
+ * its own L2; which order streams HBM faster depends on the tile shape and
+ * the domain, so the autotuner measures both. */
+typedef enum {
+  STENCIL_ORDER_AUTO = 0,    /* tuned entry, else XCD */
+  STENCIL_ORDER_XCD = 1,     /* each XCD takes one contiguous run of tiles,
+                                so tiles sharing halo rows share an L2 */
+  STENCIL_ORDER_DISPATCH = 2 /* workgroup t takes tile t: neighbouring tiles
+                                run on different XCDs at the same time */
+} stencil_tile_order;
+
 /* Optional per-call options; pass NULL for defaults. */
 /* Form of the horizontal diffusion's Laplacian stage (Sec. 3.1 names the
  * stencil; the workload's definition of it is the STATED form).  The DAMPING form
@@ -155,6 +167,8 @@ typedef struct {
                                        kappa * div; the scalar is then ignored
                                        (the adjoints take their coefficient
                                        from here too).  Read, never written. */
+  int32_t tile_order; /* stencil_tile_order of the fused step (two-ended
+                         column store); other kernels ignore it */
 } stencil_options;
 
 typedef enum {
@@ -385,7 +399,8 @@ int stencil_graph_launch(stencil_graph* graph, hipStream_t stream);
 int stencil_graph_destroy(stencil_graph* graph);
 
 /* ---------------------------------------------------------------- tuning */
-/* Times every tile candidate of `op` (STENCIL_OP_STEP, or STENCIL_OP_HDIFF,
+/* Times every tile candidate of `op` (STENCIL_OP_STEP: tile x column store,
+ * and both tile orders for the two-ended column store; or STENCIL_OP_HDIFF,
  * timed in the damping form: only the generalised diffusion's hdiff has a
  * tile; the other ops have none to choose: STENCIL_E_ARG) on a domain of this size (scratch
  * fields allocated and freed by the library for the duration of the call,
@@ -393,9 +408,21 @@ int stencil_graph_destroy(stencil_graph* graph);
  * table under (dtype, op, size class).  *best_us receives its time. */
 int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int reps,
                      double* best_us);
-/* Tile chosen for (dtype, op, domain) -- tuned entry or the default. */
+/* The step's candidates timed on the caller's own fields, on `stream` (which
+ * is synchronised before the call returns): which tile and tile order stream
+ * HBM fastest depends on where the fields sit in memory as well as on their
+ * shape, so tuning on the storages a time loop will use measures what it
+ * will run.  op must be STENCIL_OP_STEP (else STENCIL_E_ARG); the fields obey
+ * stencil_step's rules; `out` is overwritten (its interior), the inputs are
+ * only read.  Records the fastest candidate under (dtype, op, size class) as
+ * stencil_autotune does. */
+int stencil_autotune_fields(stencil_dtype dtype, int op, const stencil_field* u,
+                            const stencil_field* data, const stencil_field* w, stencil_field* out,
+                            const int64_t domain[3], int reps, hipStream_t stream, double* best_us);
+/* Tile, column store and tile order chosen for (dtype, op, domain) -- the
+ * tuned entry or the default.  tile_order may be NULL. */
 int stencil_tuning_lookup(stencil_dtype dtype, int op, const int64_t domain[3], int32_t* tile_i,
-                          int32_t* tile_j, int32_t* column_store);
+                          int32_t* tile_j, int32_t* column_store, int32_t* tile_order);
 /* Persist / restore the tuning table as JSON. */
 int stencil_save_tuning(const char* json_path);
 int stencil_load_tuning(const char* json_path);

@@ -37,6 +37,7 @@ IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN = 0, 1, 2
 COLUMN_AUTO, COLUMN_REGISTERS, COLUMN_OUTBUF, COLUMN_SPLIT = 0, 1, 2, 3
 BOUNDARY_FROZEN, BOUNDARY_PERIODIC = 0, 1
 HDIFF_STATED, HDIFF_DAMPING = 0, 1
+ORDER_AUTO, ORDER_XCD, ORDER_DISPATCH = 0, 1, 2
 OP_HDIFF, OP_VADV, OP_STEP, OP_HDIFF_ADJOINT, OP_VADV_ADJOINT, OP_STEP_ADJOINT = range(6)
 
 I64x3 = ctypes.c_int64 * 3
@@ -57,6 +58,7 @@ class StencilOptions(ctypes.Structure):
         ("boundary", ctypes.c_int32),
         ("hdiff_form", ctypes.c_int32),
         ("coeff_field", ctypes.POINTER(StencilField)),
+        ("tile_order", ctypes.c_int32),
     ]
 
 
@@ -94,7 +96,7 @@ class StencilError(RuntimeError):
 
 
 # the ABI this binding marshals for (stencil_version() of the library)
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _lock = threading.Lock()
 _lib = None
@@ -133,7 +135,8 @@ SIGNATURES = {
     "stencil_graph_launch": (I, [VP, VP]),
     "stencil_graph_destroy": (I, [VP]),
     "stencil_autotune": (I, [I, I, PI64, I, ctypes.POINTER(D)]),
-    "stencil_tuning_lookup": (I, [I, I, PI64, PI32, PI32, PI32]),
+    "stencil_autotune_fields": (I, [I, I, PF, PF, PF, PF, PI64, I, VP, ctypes.POINTER(D)]),
+    "stencil_tuning_lookup": (I, [I, I, PI64, PI32, PI32, PI32, PI32]),
     "stencil_save_tuning": (I, [ctypes.c_char_p]),
     "stencil_load_tuning": (I, [ctypes.c_char_p]),
     "stencil_clear_tuning": (I, []),

@@ -18,11 +18,11 @@ import torch
 from . import _lib
 from ._lib import (BOUNDARY_FROZEN, BOUNDARY_PERIODIC, HDIFF_DAMPING, HDIFF_STATED, COLUMN_AUTO, COLUMN_OUTBUF, COLUMN_REGISTERS, COLUMN_SPLIT, F32, F64, IMPL_AUTO, IMPL_FUSED,
                    IMPL_PLAIN, OP_HDIFF, OP_HDIFF_ADJOINT, OP_STEP, OP_STEP_ADJOINT, OP_VADV,
-                   OP_VADV_ADJOINT, StencilError)
+                   OP_VADV_ADJOINT, ORDER_AUTO, ORDER_DISPATCH, ORDER_XCD, StencilError)
 
 __all__ = [
     "Field", "Options", "StencilError", "F32", "F64",
-    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "BOUNDARY_FROZEN", "BOUNDARY_PERIODIC", "HDIFF_STATED", "HDIFF_DAMPING", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
+    "IMPL_AUTO", "IMPL_FUSED", "IMPL_PLAIN", "ORDER_AUTO", "ORDER_XCD", "ORDER_DISPATCH", "BOUNDARY_FROZEN", "BOUNDARY_PERIODIC", "HDIFF_STATED", "HDIFF_DAMPING", "COLUMN_AUTO", "COLUMN_REGISTERS", "COLUMN_OUTBUF", "COLUMN_SPLIT",
     "OP_HDIFF", "OP_VADV", "OP_STEP", "OP_HDIFF_ADJOINT", "OP_VADV_ADJOINT", "OP_STEP_ADJOINT",
     "stencil_version", "stencil_last_error", "stencil_max_fused_nk", "stencil_mask_bytes",
     "stencil_workspace_bytes", "stencil_hdiff", "stencil_vadv", "stencil_step",
@@ -31,7 +31,8 @@ __all__ = [
     "stencil_halo_update",
     "stencil_batch_workspace_bytes", "stencil_batch_adjoint_workspace_bytes",
     "stencil_step_batched", "stencil_step_adjoint_batched", "stencil_graph_capture_steps",
-    "stencil_graph_launch", "stencil_graph_destroy", "stencil_autotune", "stencil_tuning_lookup",
+    "stencil_graph_launch", "stencil_graph_destroy", "stencil_autotune", "stencil_autotune_fields",
+    "stencil_tuning_lookup",
     "stencil_save_tuning", "stencil_load_tuning", "stencil_clear_tuning",
 ]
 
@@ -67,6 +68,7 @@ class Options:
     boundary: int = BOUNDARY_FROZEN
     hdiff_form: int = HDIFF_STATED
     coeff_field: Optional["Field"] = None  # per-point coefficient (interior layout)
+    tile_order: int = ORDER_AUTO
 
     def c(self) -> _lib.StencilOptions:
         o = _lib.StencilOptions()
@@ -79,6 +81,7 @@ class Options:
             o.workspace_bytes = self.workspace.numel() * self.workspace.element_size()
         o.boundary = self.boundary
         o.hdiff_form = self.hdiff_form
+        o.tile_order = self.tile_order
         if self.coeff_field is not None:
             cf = self.coeff_field if isinstance(self.coeff_field, _lib.StencilField) else self.coeff_field.c()
             o._coeff_field = cf  # keep the descriptor alive with the options
@@ -306,11 +309,21 @@ def stencil_autotune(dtype, op, domain, reps=5) -> float:
     return us.value
 
 
+def stencil_autotune_fields(u, data, w, out, domain, reps=5, op=OP_STEP, stream=None, dtype=None) -> float:
+    """Tune the step on these fields (out is overwritten); returns the best time in us."""
+    us = ctypes.c_double()
+    _lib.check(_lib.lib().stencil_autotune_fields(_dt(dtype, u, out), int(op), _fld(u), _fld(data), _fld(w),
+                                                  _fld(out), _lib.domain3(domain), int(reps), _stream(stream),
+                                                  ctypes.byref(us)))
+    return us.value
+
+
 def stencil_tuning_lookup(dtype, op, domain):
-    ti, tj, col = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(tile_i, tile_j, column_store, tile_order) chosen for this size class."""
+    ti, tj, col, order = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _lib.check(_lib.lib().stencil_tuning_lookup(_dt(dtype), int(op), _lib.domain3(domain), ctypes.byref(ti),
-                                                ctypes.byref(tj), ctypes.byref(col)))
-    return ti.value, tj.value, col.value
+                                                ctypes.byref(tj), ctypes.byref(col), ctypes.byref(order)))
+    return ti.value, tj.value, col.value, order.value
 
 
 def stencil_save_tuning(path: str):

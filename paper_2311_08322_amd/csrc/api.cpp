@@ -144,8 +144,8 @@ int check_no_alias(const char* oname, Span o, const char* iname, Span in) {
 ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, const int64_t* dom) {
   ResolvedOpts r;
   r.impl = o ? o->impl : STENCIL_IMPL_AUTO;
-  int32_t ti = 0, tj = 0, col = 0;
-  tuning_get(dt, op, dom, &ti, &tj, &col);
+  int32_t ti = 0, tj = 0, col = 0, ord = 0;
+  tuning_get(dt, op, dom, &ti, &tj, &col, &ord);
   r.tile_i = (o && o->tile_i) ? o->tile_i : ti;
   r.column_store = (o && o->column_store) ? o->column_store : col;
   if (r.column_store == STENCIL_COLUMN_AUTO) {
@@ -158,6 +158,8 @@ ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, co
   r.ws_bytes = o ? o->workspace_bytes : 0;
   r.form = o ? o->hdiff_form : STENCIL_HDIFF_STATED;
   r.kappa = o ? o->coeff_field : nullptr;
+  r.order = (o && o->tile_order) ? o->tile_order : ord;
+  if (r.order != STENCIL_ORDER_DISPATCH) r.order = STENCIL_ORDER_XCD;
   return r;
 }
 
@@ -177,6 +179,8 @@ int check_opts(const stencil_options* o) {
     return fail(STENCIL_E_ARG, "options.boundary = %d unknown", (int)o->boundary);
   if (o->hdiff_form != STENCIL_HDIFF_STATED && o->hdiff_form != STENCIL_HDIFF_DAMPING)
     return fail(STENCIL_E_ARG, "options.hdiff_form = %d unknown", (int)o->hdiff_form);
+  if (o->tile_order < STENCIL_ORDER_AUTO || o->tile_order > STENCIL_ORDER_DISPATCH)
+    return fail(STENCIL_E_ARG, "options.tile_order = %d unknown", (int)o->tile_order);
   return STENCIL_OK;
 }
 
@@ -336,6 +340,7 @@ int run_step(const stencil_field* u, const stencil_field* data, const stencil_fi
   }
   StepArgs<T> A = step_args<T>(u, data, w, out, dom, coeff, dt_dz, mask);
   apply_variant(A, r);
+  A.order = r.order;
   return hip_status(launch_step_fused<T>(A, r.tile_i, r.column_store, s), "step (fused)");
 }
 

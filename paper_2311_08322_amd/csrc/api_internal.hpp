@@ -46,6 +46,7 @@ struct ResolvedOpts {
   size_t ws_bytes;
   int form;                    // stencil_hdiff_form
   const stencil_field* kappa;  // per-point coefficient or null
+  int order;                   // stencil_tile_order (resolved: XCD or DISPATCH)
 };
 // options that ask for the generalised diffusion
 inline bool variant_opts(const stencil_options* o) {
@@ -88,8 +89,9 @@ int check_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items
 int launch_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
                       const stencil_options* opts, hipStream_t stream);
 
-// tuning table (tune.cpp): tile and column store for (dtype, op, size class)
+// tuning table (tune.cpp): tile, column store and tile order for (dtype, op,
+// size class)
 void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* tile_i, int32_t* tile_j,
-                int32_t* column_store);
+                int32_t* column_store, int32_t* tile_order);
 
 }  // namespace gt4mi

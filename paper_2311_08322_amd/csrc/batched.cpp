@@ -52,8 +52,8 @@ int tile_i_of(const stencil_options* o, stencil_dtype dt, int op, int n, const I
     if (p > most) most = p, best = a;
   }
   if (best < 0) return 64;
-  int32_t ti = 64, tj = 4, col = 0;
-  tuning_get(dt, op, it[best].domain, &ti, &tj, &col);
+  int32_t ti = 64, tj = 4, col = 0, ord = 0;
+  tuning_get(dt, op, it[best].domain, &ti, &tj, &col, &ord);
   return (ti == 16 || ti == 32) ? ti : 64;
 }
 

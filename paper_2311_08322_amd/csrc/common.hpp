@@ -54,6 +54,11 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
   const int x = b % kNumXcd, local = b / kNumXcd;
   return x * q + (x < r ? x : r) + local;
 }
+// The tile of workgroup b in the given order (stencil_tile_order: 2 takes
+// the dispatch order itself, anything else the XCD runs).
+__device__ __forceinline__ int ordered_tile(int order, int b, int nblocks) {
+  return order == 2 ? b : xcd_tile(b, nblocks);
+}
 
 // ------------------------------------------------------------ addressing
 // Fields are read and written through buffer resources: a per-level
@@ -213,6 +218,7 @@ struct StepArgs {
   const T* kappa;  // per-point coefficient at domain (0,0,0), or null (scalar coeff)
   int64_t c_sj, c_sk;
   int form;  // 0: lap = 4u - sum of the neighbours; 1: the damping form, lap = sum - 4u
+  int order;  // tile order of the two-ended step: 2 = dispatch order, else XCD runs
 };
 
 // Sign that folds the damping form into the stated one: its Laplacian,

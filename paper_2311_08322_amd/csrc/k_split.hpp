@@ -253,7 +253,7 @@ __device__ __forceinline__ void step_split_tile(const StepArgs<T>& A, int tile, 
 template <typename T, int TI, int TJ, int NKH, int PD, bool MASK, int COL, bool VAR>
 __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
   __shared__ SplitSmem<T, TI, TJ> sm;
-  step_split_tile<T, TI, TJ, NKH, PD, MASK, COL, VAR>(A, xcd_tile(blockIdx.x, gridDim.x), sm);
+  step_split_tile<T, TI, TJ, NKH, PD, MASK, COL, VAR>(A, ordered_tile(A.order, blockIdx.x, gridDim.x), sm);
 }
 
 // One instantiation per half-column register class.  With the early exit a

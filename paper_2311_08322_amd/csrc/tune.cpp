@@ -1,8 +1,9 @@
 // tune.cpp -- the autotuner and its process-wide tuning table.
 //
 // A tuning entry is keyed by (dtype, op, nk class, area class) and holds the
-// horizontal tile (64x4, 32x8 or 16x16) and the column store of the fused
-// kernels.  stencil_autotune times every candidate on scratch fields of the
+// horizontal tile (64x4, 32x8 or 16x16), the column store of the fused
+// kernels and the order in which the two-ended step's workgroups take their
+// tiles (XCD runs or dispatch order).  stencil_autotune times every candidate on scratch fields of the
 // requested size; the table persists as JSON (an analogue of the paper's
 // build cache, Sec. 2.3, keyed by size class instead of source fingerprint).
 #include <hip/hip_runtime.h>
@@ -11,6 +12,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -30,7 +32,7 @@ struct TuneKey {
   }
 };
 struct TuneVal {
-  int tile_i, tile_j, col;
+  int tile_i, tile_j, col, order;
   double us;
 };
 
@@ -43,7 +45,8 @@ static int area_class(int64_t ni, int64_t nj) {
   return a < 128 * 128 ? 0 : (a < 256 * 256 ? 1 : 2);
 }
 
-void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32_t* tj, int32_t* col) {
+void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32_t* tj, int32_t* col,
+                int32_t* order) {
   TuneKey k{(int)dt, op, nk_class(dom[2]), area_class(dom[0], dom[1])};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_table.find(k);
@@ -51,10 +54,12 @@ void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32
     *ti = it->second.tile_i;
     *tj = it->second.tile_j;
     *col = it->second.col;
+    *order = it->second.order;
   } else {
     *ti = 64;
     *tj = 4;
     *col = STENCIL_COLUMN_AUTO;
+    *order = STENCIL_ORDER_XCD;
   }
 }
 
@@ -77,75 +82,56 @@ struct Scratch {
   }
 };
 
-stencil_field make_field(void* p, int64_t ni, int64_t nj, int64_t nk, int64_t halo, int64_t kextra) {
+// The layout the Python storages use (and so the one worth tuning for):
+// the first interior point of every row on a 128-byte line and the row pitch
+// a multiple of 128 bytes.
+constexpr int64_t kLine = 128;
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int64_t field_elems(int64_t ni, int64_t nj, int64_t nk, int64_t halo, int64_t kextra, size_t es) {
+  const int64_t a = kLine / (int64_t)es;
+  const int64_t oi = halo ? round_up(halo, a) : 0;
+  return round_up(oi + std::max<int64_t>(ni, 1) + halo, a) * (nj + 2 * halo) * (nk + kextra);
+}
+
+stencil_field make_field(void* p, int64_t ni, int64_t nj, int64_t nk, int64_t halo, int64_t kextra, size_t es) {
+  const int64_t a = kLine / (int64_t)es;
+  const int64_t oi = halo ? round_up(halo, a) : 0;
   stencil_field f;
   f.data = p;
-  f.shape[0] = ni + 2 * halo;
+  f.shape[0] = round_up(oi + std::max<int64_t>(ni, 1) + halo, a);
   f.shape[1] = nj + 2 * halo;
   f.shape[2] = nk + kextra;
   f.stride[0] = 1;
   f.stride[1] = f.shape[0];
   f.stride[2] = f.shape[0] * f.shape[1];
-  f.origin[0] = halo;
+  f.origin[0] = oi;
   f.origin[1] = halo;
   f.origin[2] = 0;
   return f;
 }
 
-}  // namespace
 
-extern "C" {
-
-int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int reps, double* best_us) {
-  if (check_dtype(dtype)) return STENCIL_E_DTYPE;
-  if (int rc = check_domain(domain)) return rc;
-  if (domain_empty(domain)) return fail(STENCIL_E_SHAPE, "cannot tune an empty domain");
-  // the adjoints' gather walks fixed strips and their column solve has no
-  // tile: only the forward kernels have a tile to choose
-  if (op != STENCIL_OP_STEP && op != STENCIL_OP_HDIFF)
-    return fail(STENCIL_E_ARG, "op %d has no tile choice to tune", op);
-  if (reps <= 0) reps = 5;
-  if (int rc = check_device()) return rc;
+// Times every candidate of `op` on the given fields (on stream s) and
+// records the fastest under (dtype, op, size class).  `out` is overwritten.
+int tune_candidates(stencil_dtype dtype, int op, const stencil_field* u, const stencil_field* data,
+                    const stencil_field* w, stencil_field* out, void* pm, void* pws, size_t wsb,
+                    const int64_t domain[3], int reps, hipStream_t s, double* best_us) {
   const int64_t ni = domain[0], nj = domain[1], nk = domain[2];
-  const size_t es = esize(dtype);
-  const size_t padded = (size_t)((ni + 4) * (nj + 4) * nk) * es;
-  const size_t inter = (size_t)(ni * nj * nk) * es;
-  const size_t stag = (size_t)(ni * nj * (nk + 1)) * es;
-  Scratch sc;
-  void* pu = sc.alloc(padded);
-  void* po = sc.alloc(padded);
-  void* pd = sc.alloc(inter);
-  void* pw = sc.alloc(stag);
-  void* pm = sc.alloc(stencil_mask_bytes(domain));
-  const size_t wsb = stencil_workspace_bytes(op, dtype, domain, nullptr);
-  void* pws = wsb ? sc.alloc(wsb) : nullptr;
-  if (!pu || !po || !pd || !pw || !pm || (wsb && !pws))
-    return fail(STENCIL_E_HIP, "autotune: scratch allocation failed");
-  hipStream_t s;
-  if (hipStreamCreate(&s) != hipSuccess) return fail(STENCIL_E_HIP, "autotune: stream");
-  auto fill = [&](void* p, size_t bytes, double lo, double hi, uint32_t seed) {
-    const int64_t n = (int64_t)(bytes / es);
-    if (dtype == STENCIL_F64) launch_fill_pattern<double>((double*)p, n, lo, hi, seed, s);
-    else launch_fill_pattern<float>((float*)p, n, (float)lo, (float)hi, seed, s);
-  };
-  fill(pu, padded, 0.0, 1.0, 1u);
-  fill(po, padded, 0.0, 1.0, 2u);
-  fill(pd, inter, -0.1, 0.1, 3u);
-  fill(pw, stag, -1.0, 1.0, 4u);
-  stencil_field u = make_field(pu, ni, nj, nk, 2, 0), out = make_field(po, ni, nj, nk, 2, 0);
-  stencil_field data = make_field(pd, ni, nj, nk, 0, 0), w = make_field(pw, ni, nj, nk, 0, 1);
   int rc = 0;
   struct Cand {
-    int ti, tj, col;
+    int ti, tj, col, order;
   };
   std::vector<Cand> cands;
   for (int t : {64, 32, 16}) {
     if (op == STENCIL_OP_STEP) {
-      if (nk <= split_step_limit((int)(dtype == STENCIL_F64 ? 8 : 4))) cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT});
-      if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS});
-      if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF});
+      if (nk <= split_step_limit((int)(dtype == STENCIL_F64 ? 8 : 4)))
+        for (int ord : {STENCIL_ORDER_XCD, STENCIL_ORDER_DISPATCH})
+          cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT, ord});
+      if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS, STENCIL_ORDER_XCD});
+      if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF, STENCIL_ORDER_XCD});
     } else {
-      cands.push_back({t, 256 / t, STENCIL_COLUMN_AUTO});  // hdiff
+      cands.push_back({t, 256 / t, STENCIL_COLUMN_AUTO, STENCIL_ORDER_XCD});  // hdiff
     }
   }
   hipEvent_t e0, e1;
@@ -160,6 +146,7 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
     o.tile_i = c.ti;
     o.tile_j = c.tj;
     o.column_store = c.col;
+    o.tile_order = c.order;
     o.workspace = pws;
     o.workspace_bytes = wsb;
     // the stated hdiff walks fixed strips; the tile is the generalised
@@ -167,23 +154,38 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
     if (op == STENCIL_OP_HDIFF) o.hdiff_form = STENCIL_HDIFF_DAMPING;
     auto run = [&]() -> int {
       switch (op) {
-        case STENCIL_OP_STEP: return stencil_step(dtype, &u, &data, &w, &out, domain, 0.025, 0.5, pm, &o, s);
-        default: return stencil_hdiff(dtype, &u, &out, domain, 0.025, pm, &o, s);
+        // the step as a time loop runs it: without saving the limiter mask
+        case STENCIL_OP_STEP: return stencil_step(dtype, u, data, w, out, domain, 0.025, 0.5, nullptr, &o, s);
+        default: return stencil_hdiff(dtype, u, out, domain, 0.025, pm, &o, s);
       }
     };
-    rc = run();  // warm-up
-    if (rc) break;
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && !rc; ++r) rc = run();
-    (void)hipEventRecord(e1, s);
-    if (rc) break;
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      rc = fail(STENCIL_E_HIP, "autotune: event sync");
-      break;
+    // A window of `reps` back-to-back calls, timed with events.
+    auto window = [&](double* us) -> int {
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) TRY(run());
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) return fail(STENCIL_E_HIP, "autotune: event sync");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      *us = 1000.0 * ms / reps;
+      return STENCIL_OK;
+    };
+    // Warm-up: after a change of candidate the calls run measurably slower
+    // for several milliseconds (the caches, the last-level one included,
+    // still hold what the previous order left), so windows run until at
+    // least 10 ms of device time has passed; then the median of three
+    // windows counts.
+    double us = 0.0, warm = 0.0;
+    for (int n = 0; n < 256 && warm < 10000.0 && !rc; ++n) {
+      rc = window(&us);
+      warm += us * reps;
     }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const double us = 1000.0 * ms / reps;
+    if (rc) break;
+    double t3[3];
+    for (int n = 0; n < 3 && !rc; ++n) rc = window(&t3[n]);
+    if (rc) break;
+    std::sort(t3, t3 + 3);
+    us = t3[1];
     if (us < best) {
       best = us;
       bc = c;
@@ -192,22 +194,95 @@ int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int r
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipStreamDestroy(s);
   if (rc) return rc;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_table[TuneKey{(int)dtype, op, nk_class(nk), area_class(ni, nj)}] = TuneVal{bc.ti, bc.tj, bc.col, best};
+    g_table[TuneKey{(int)dtype, op, nk_class(nk), area_class(ni, nj)}] = TuneVal{bc.ti, bc.tj, bc.col, bc.order, best};
   }
   if (best_us) *best_us = best;
   return STENCIL_OK;
 }
 
+int check_tune_args(stencil_dtype dtype, int op, const int64_t domain[3]) {
+  if (check_dtype(dtype)) return STENCIL_E_DTYPE;
+  TRY(check_domain(domain));
+  if (domain_empty(domain)) return fail(STENCIL_E_SHAPE, "cannot tune an empty domain");
+  // the adjoints' gather walks fixed strips and their column solve has no
+  // tile: only the forward kernels have a tile to choose
+  if (op != STENCIL_OP_STEP && op != STENCIL_OP_HDIFF)
+    return fail(STENCIL_E_ARG, "op %d has no tile choice to tune", op);
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stencil_autotune(stencil_dtype dtype, int op, const int64_t domain[3], int reps, double* best_us) {
+  TRY(check_tune_args(dtype, op, domain));
+  if (reps <= 0) reps = 5;
+  TRY(check_device());
+  const int64_t ni = domain[0], nj = domain[1], nk = domain[2];
+  const size_t es = esize(dtype);
+  const size_t padded = (size_t)field_elems(ni, nj, nk, 2, 0, es) * es;
+  const size_t inter = (size_t)field_elems(ni, nj, nk, 0, 0, es) * es;
+  const size_t stag = (size_t)field_elems(ni, nj, nk, 0, 1, es) * es;
+  Scratch sc;
+  void* pu = sc.alloc(padded);
+  void* po = sc.alloc(padded);
+  void* pd = sc.alloc(inter);
+  void* pw = sc.alloc(stag);
+  void* pm = sc.alloc(stencil_mask_bytes(domain));
+  const size_t wsb = stencil_workspace_bytes(op, dtype, domain, nullptr);
+  void* pws = wsb ? sc.alloc(wsb) : nullptr;
+  if (!pu || !po || !pd || !pw || !pm || (wsb && !pws))
+    return fail(STENCIL_E_HIP, "autotune: scratch allocation failed");
+  hipStream_t s;
+  if (hipStreamCreate(&s) != hipSuccess) return fail(STENCIL_E_HIP, "autotune: stream");
+  auto fill = [&](void* p, size_t bytes, double lo, double hi, uint32_t seed) {
+    const int64_t n = (int64_t)(bytes / es);
+    if (dtype == STENCIL_F64) (void)launch_fill_pattern<double>((double*)p, n, lo, hi, seed, s);
+    else (void)launch_fill_pattern<float>((float*)p, n, (float)lo, (float)hi, seed, s);
+  };
+  fill(pu, padded, 0.0, 1.0, 1u);
+  fill(po, padded, 0.0, 1.0, 2u);
+  fill(pd, inter, -0.1, 0.1, 3u);
+  fill(pw, stag, -1.0, 1.0, 4u);
+  stencil_field u = make_field(pu, ni, nj, nk, 2, 0, es), out = make_field(po, ni, nj, nk, 2, 0, es);
+  stencil_field data = make_field(pd, ni, nj, nk, 0, 0, es), w = make_field(pw, ni, nj, nk, 0, 1, es);
+  const int rc = tune_candidates(dtype, op, &u, &data, &w, &out, pm, pws, wsb, domain, reps, s, best_us);
+  (void)hipStreamSynchronize(s);
+  (void)hipStreamDestroy(s);
+  return rc;
+}
+
+int stencil_autotune_fields(stencil_dtype dtype, int op, const stencil_field* u, const stencil_field* data,
+                            const stencil_field* w, stencil_field* out, const int64_t domain[3], int reps,
+                            hipStream_t stream, double* best_us) {
+  TRY(check_tune_args(dtype, op, domain));
+  if (op != STENCIL_OP_STEP) return fail(STENCIL_E_ARG, "tuning on caller fields covers STENCIL_OP_STEP");
+  if (reps <= 0) reps = 5;
+  const size_t es = esize(dtype);
+  TRY(check_field("u", u, domain, ROLE_HALO, es));
+  TRY(check_field("data", data, domain, ROLE_INTERIOR, es));
+  TRY(check_field("w", w, domain, ROLE_STAGGERED, es));
+  TRY(check_field("out", out, domain, ROLE_INTERIOR, es));
+  const Span so = span_of(out, es);
+  TRY(check_no_alias("out", so, "u", span_of(u, es)));
+  TRY(check_no_alias("out", so, "data", span_of(data, es)));
+  TRY(check_no_alias("out", so, "w", span_of(w, es)));
+  TRY(check_device());
+  return tune_candidates(dtype, op, u, data, w, out, nullptr, nullptr, 0, domain, reps, stream, best_us);
+}
+
 int stencil_tuning_lookup(stencil_dtype dtype, int op, const int64_t domain[3], int32_t* tile_i,
-                          int32_t* tile_j, int32_t* column_store) {
+                          int32_t* tile_j, int32_t* column_store, int32_t* tile_order) {
   if (int rc = check_dtype(dtype)) return rc;
   if (int rc = check_domain(domain)) return rc;
   if (!tile_i || !tile_j || !column_store) return fail(STENCIL_E_NULL, "output pointer is NULL");
-  tuning_get(dtype, op, domain, tile_i, tile_j, column_store);
+  int32_t ord = 0;
+  tuning_get(dtype, op, domain, tile_i, tile_j, column_store, &ord);
+  if (tile_order) *tile_order = ord;
   return STENCIL_OK;
 }
 
@@ -227,9 +302,9 @@ int stencil_save_tuning(const char* path) {
   for (const auto& kv : g_table) {
     fprintf(f,
             "  {\"dtype\": %d, \"op\": %d, \"nk_class\": %d, \"area_class\": %d, \"tile_i\": %d, "
-            "\"tile_j\": %d, \"column_store\": %d, \"us\": %.3f}%s\n",
+            "\"tile_j\": %d, \"column_store\": %d, \"tile_order\": %d, \"us\": %.3f}%s\n",
             kv.first.dtype, kv.first.op, kv.first.nkc, kv.first.areac, kv.second.tile_i,
-            kv.second.tile_j, kv.second.col, kv.second.us, (++n < g_table.size()) ? "," : "");
+            kv.second.tile_j, kv.second.col, kv.second.order, kv.second.us, (++n < g_table.size()) ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -269,6 +344,7 @@ int stencil_load_tuning(const char* path) {
     TuneKey k;
     TuneVal v;
     v.us = 0.0;
+    v.order = STENCIL_ORDER_XCD;  // tables written before the order was tuned
     if (!read_int(p, e, "dtype", &k.dtype) || !read_int(p, e, "op", &k.op) ||
         !read_int(p, e, "nk_class", &k.nkc) || !read_int(p, e, "area_class", &k.areac) ||
         !read_int(p, e, "tile_i", &v.tile_i) || !read_int(p, e, "tile_j", &v.tile_j) ||
@@ -278,6 +354,9 @@ int stencil_load_tuning(const char* path) {
           (v.tile_i == 16 && v.tile_j == 16)) ||
         v.col < 0 || v.col > STENCIL_COLUMN_SPLIT)
       return fail(STENCIL_E_ARG, "%s: entry with unsupported tile or column store", path);
+    if (read_int(p, e, "tile_order", &v.order) &&
+        v.order != STENCIL_ORDER_XCD && v.order != STENCIL_ORDER_DISPATCH)
+      return fail(STENCIL_E_ARG, "%s: entry with unsupported tile order", path);
     const char* us = strstr(p, "\"us\":");
     if (us && us < e) v.us = strtod(us + 5, nullptr);
     t[k] = v;

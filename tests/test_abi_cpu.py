@@ -40,7 +40,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_limits(L):
-    assert L.stencil_version() == 2
+    assert L.stencil_version() == 3
     assert L.stencil_max_fused_nk(1) >= 137
 
 
@@ -252,32 +252,49 @@ def test_graph_capture_validation(L):
 def test_tuning_json_roundtrip(L, tmp_path):
     assert L.stencil_clear_tuning() == 0
     d = _lib.domain3((256, 256, 80))
-    ti, tj, col = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
-    assert (ti.value, tj.value) == (64, 4)
+    ti, tj, col, order = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+
+    def look(dom):
+        return L.stencil_tuning_lookup(1, _lib.OP_STEP, dom, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col),
+                                       ctypes.byref(order))
+
+    assert look(d) == 0
+    assert (ti.value, tj.value, order.value) == (64, 4, _lib.ORDER_XCD)
+    # the order output may be NULL
+    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col),
+                                   None) == 0
     p = tmp_path / "tune.json"
     doc = {"arch": "gfx950", "version": 1, "entries": [
         {"dtype": 1, "op": _lib.OP_STEP, "nk_class": 5, "area_class": 2, "tile_i": 32, "tile_j": 8,
          "column_store": 2, "us": 12.5}]}
     p.write_text(json.dumps(doc))
     assert L.stencil_load_tuning(str(p).encode()) == 0
-    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
-    assert (ti.value, tj.value, col.value) == (32, 8, 2)
+    assert look(d) == 0
+    # an entry without a tile order (an older table) takes the XCD runs
+    assert (ti.value, tj.value, col.value, order.value) == (32, 8, 2, _lib.ORDER_XCD)
     # another size class is untouched
     d2 = _lib.domain3((64, 64, 16))
-    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d2, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
+    assert look(d2) == 0
     assert ti.value == 64
+    doc["entries"][0]["tile_order"] = _lib.ORDER_DISPATCH
+    doc["entries"][0]["column_store"] = 3
+    p.write_text(json.dumps(doc))
+    assert L.stencil_load_tuning(str(p).encode()) == 0
+    assert look(d) == 0 and (col.value, order.value) == (3, _lib.ORDER_DISPATCH)
     q = tmp_path / "saved.json"
     assert L.stencil_save_tuning(str(q).encode()) == 0
     saved = json.loads(q.read_text())
     assert saved["arch"] == "gfx950" and len(saved["entries"]) == 1
-    assert saved["entries"][0]["tile_i"] == 32
+    assert saved["entries"][0]["tile_i"] == 32 and saved["entries"][0]["tile_order"] == _lib.ORDER_DISPATCH
     assert L.stencil_clear_tuning() == 0
     assert L.stencil_load_tuning(str(q).encode()) == 0
-    assert L.stencil_tuning_lookup(1, _lib.OP_STEP, d, ctypes.byref(ti), ctypes.byref(tj), ctypes.byref(col)) == 0
-    assert ti.value == 32
+    assert look(d) == 0
+    assert ti.value == 32 and order.value == _lib.ORDER_DISPATCH
     bad = tmp_path / "bad.json"
     bad.write_text('{"arch": "gfx950", "entries": [{"dtype": 1, "op": 2, "tile_i": 48}]}')
+    assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
+    doc["entries"][0]["tile_order"] = 7
+    bad.write_text(json.dumps(doc))
     assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
     assert L.stencil_load_tuning(b"/nonexistent/x.json") == code("STENCIL_E_ARG")
     assert L.stencil_clear_tuning() == 0
@@ -446,6 +463,34 @@ def test_boundary_option_and_halo_update_validation(L):
     items = batch_items([(16, 12, 8)])
     assert L.stencil_step_batched(1, 1, items, BASE + (64 << 32), 1 << 20, b(o), None) == code(
         "STENCIL_E_UNSUPPORTED")
+
+
+def test_autotune_fields_validation(L):
+    """Tuning on caller fields: only the step, the step's field rules, no
+    output overlapping an input -- all refused before any device work."""
+    b = ctypes.byref
+    u, data, w, out, d = fields()
+    us = ctypes.c_double()
+    assert L.stencil_autotune_fields(1, _lib.OP_HDIFF, b(u), b(data), b(w), b(out), d, 2, None, b(us)) == code(
+        "STENCIL_E_ARG")
+    assert L.stencil_autotune_fields(1, _lib.OP_STEP, b(u), b(data), b(w), b(u), d, 2, None, b(us)) == code(
+        "STENCIL_E_ALIAS")
+    assert L.stencil_autotune_fields(1, _lib.OP_STEP, None, b(data), b(w), b(out), d, 2, None, b(us)) == code(
+        "STENCIL_E_NULL")
+    assert L.stencil_autotune_fields(7, _lib.OP_STEP, b(u), b(data), b(w), b(out), d, 2, None, b(us)) == code(
+        "STENCIL_E_DTYPE")
+    assert L.stencil_autotune_fields(1, _lib.OP_STEP, b(u), b(data), b(w), b(out), _lib.domain3((0, 4, 4)), 2,
+                                     None, b(us)) == code("STENCIL_E_SHAPE")
+
+
+def test_tile_order_validation(L):
+    """An unknown tile order is refused before any device work."""
+    u, data, w, out, d = fields()
+    o = _lib.StencilOptions()
+    for bad in (-1, 3):
+        o.tile_order = bad
+        assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+        assert "tile_order" in _lib.last_error()
 
 
 def test_generalised_diffusion_validation(L):

@@ -25,8 +25,8 @@ def _ref_inputs(f, dtype):
     return f
 
 
-def _opts(impl, tile=0, col=0, dtype=torch.float64, dom=None, op=api.OP_STEP):
-    o = api.Options(impl=impl, tile_i=tile, tile_j=(256 // tile if tile else 0), column_store=col)
+def _opts(impl, tile=0, col=0, dtype=torch.float64, dom=None, op=api.OP_STEP, order=api.ORDER_AUTO):
+    o = api.Options(impl=impl, tile_i=tile, tile_j=(256 // tile if tile else 0), column_store=col, tile_order=order)
     if impl == api.IMPL_PLAIN or (dom is not None and dom[2] > api.stencil_max_fused_nk()):
         o.workspace = fields.workspace(op, dtype, dom, o)
     return o
@@ -124,19 +124,21 @@ STEP_CASES = [(64, 64, 16), (100, 37, 80), (67, 45, 7), (1, 1, 1), (9, 5, 2), (3
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
-@pytest.mark.parametrize("impl,tile,col", [
-    (api.IMPL_PLAIN, 0, 0),
-    (api.IMPL_FUSED, 64, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 64, api.COLUMN_OUTBUF),
-    (api.IMPL_FUSED, 32, api.COLUMN_REGISTERS), (api.IMPL_FUSED, 16, api.COLUMN_OUTBUF),
-    (api.IMPL_FUSED, 64, api.COLUMN_SPLIT), (api.IMPL_FUSED, 32, api.COLUMN_SPLIT),
-    (api.IMPL_FUSED, 16, api.COLUMN_SPLIT), (api.IMPL_AUTO, 0, 0)],
-    ids=["plain", "t64reg", "t64out", "t32reg", "t16out", "t64split", "t32split", "t16split", "auto"])
+@pytest.mark.parametrize("impl,tile,col,order", [
+    (api.IMPL_PLAIN, 0, 0, 0),
+    (api.IMPL_FUSED, 64, api.COLUMN_REGISTERS, 0), (api.IMPL_FUSED, 64, api.COLUMN_OUTBUF, 0),
+    (api.IMPL_FUSED, 32, api.COLUMN_REGISTERS, 0), (api.IMPL_FUSED, 16, api.COLUMN_OUTBUF, 0),
+    (api.IMPL_FUSED, 64, api.COLUMN_SPLIT, api.ORDER_XCD), (api.IMPL_FUSED, 32, api.COLUMN_SPLIT, api.ORDER_XCD),
+    (api.IMPL_FUSED, 16, api.COLUMN_SPLIT, api.ORDER_XCD), (api.IMPL_FUSED, 64, api.COLUMN_SPLIT, api.ORDER_DISPATCH),
+    (api.IMPL_FUSED, 32, api.COLUMN_SPLIT, api.ORDER_DISPATCH), (api.IMPL_AUTO, 0, 0, 0)],
+    ids=["plain", "t64reg", "t64out", "t32reg", "t16out", "t64split", "t32split", "t16split", "t64split_dispatch",
+         "t32split_dispatch", "auto"])
 @pytest.mark.parametrize("dims", STEP_CASES, ids=lambda d: "x".join(map(str, d)))
-def test_step(dims, impl, tile, col, dtype):
+def test_step(dims, impl, tile, col, order, dtype):
     ni, nj, nk = dims
     if nk > api.stencil_max_fused_nk() and impl == api.IMPL_FUSED:
         pytest.skip("longer than the fused classes (covered by plain/auto)")
-    print(f"step {dims} impl={impl} tile={tile} col={col} {dtype}", flush=True)
+    print(f"step {dims} impl={impl} tile={tile} col={col} order={order} {dtype}", flush=True)
     f = inputs.fields_sized(ni, nj, nk, seed=103)
     r = _ref_inputs(f, dtype)
     u, data, w = dev_fields(f, dtype, DEV)
@@ -144,7 +146,7 @@ def test_step(dims, impl, tile, col, dtype):
     mask = fields.mask_tensor(dims, DEV)
     coeff = c_scalar(inputs.COEFF, dtype)
     api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask,
-                     opts=_opts(impl, tile, col, dtype, dims, api.OP_STEP))
+                     opts=_opts(impl, tile, col, dtype, dims, api.OP_STEP, order))
     torch.cuda.synchronize()
     ref, mx, my = orc.step(r.u, r.data, r.w, coeff, inputs.DT_DZ, decide_f32=(dtype == torch.float32))
     assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
@@ -191,6 +193,76 @@ def test_step_full_size(wl, dtype):
     assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
     gmx, gmy = unpack_mask(mask, ni, nj, nk)
     assert np.array_equal(gmx, mx) and np.array_equal(gmy, my)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("tile", [64, 32, 16])
+def test_step_tile_orders_agree_full_size(tile, dtype):
+    """Both tile orders compute every column with the same operations: the
+    512x512x80 step and its masks agree bit for bit between them."""
+    wl = inputs.STEP_512
+    dims = (wl.ni, wl.nj, wl.nk)
+    print(f"step tile orders {dims} tile {tile} {dtype}", flush=True)
+    f = inputs.fields_for(wl)
+    u, data, w = dev_fields(f, dtype, DEV)
+    res = []
+    for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
+        out = fields.alloc(*dims, dtype, DEV, fill=0.0)
+        mask = fields.mask_tensor(dims, DEV)
+        api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask,
+                         opts=_opts(api.IMPL_FUSED, tile, api.COLUMN_SPLIT, dtype, dims, api.OP_STEP, order))
+        res.append((out, mask))
+    torch.cuda.synchronize()
+    assert torch.equal(fields.interior(res[0][0], *dims), fields.interior(res[1][0], *dims))
+    assert torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_autotune_step_and_tuned_step(dtype):
+    """The step's autotuner records a supported tile, column store and tile
+    order for the size class, and the step run with the tuned entry matches
+    the oracle."""
+    dims = (150, 70, 40)
+    print(f"autotune step {dims} {dtype}", flush=True)
+    api.stencil_clear_tuning()
+    best = api.stencil_autotune(dtype, api.OP_STEP, dims, reps=2)
+    assert best > 0
+    ti, tj, col, order = api.stencil_tuning_lookup(dtype, api.OP_STEP, dims)
+    assert (ti, tj) in ((64, 4), (32, 8), (16, 16))
+    assert col in (api.COLUMN_REGISTERS, api.COLUMN_OUTBUF, api.COLUMN_SPLIT)
+    assert order in (api.ORDER_XCD, api.ORDER_DISPATCH)
+    f = inputs.fields_sized(*dims, seed=108)
+    r = _ref_inputs(f, dtype)
+    u, data, w = dev_fields(f, dtype, DEV)
+    out = fields.alloc(*dims, dtype, DEV, fill=0.0)
+    api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ)
+    torch.cuda.synchronize()
+    ref, _, _ = orc.step(r.u, r.data, r.w, c_scalar(inputs.COEFF, dtype), inputs.DT_DZ,
+                         decide_f32=(dtype == torch.float32))
+    assert rel_err(host(fields.interior(out, *dims)), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
+    api.stencil_clear_tuning()
+
+
+def test_autotune_on_fields_then_step():
+    """Tuning on the caller's fields leaves the inputs as they were, records
+    a supported entry, and the step with it matches the oracle."""
+    dims = (130, 90, 60)
+    print(f"autotune on fields {dims}", flush=True)
+    api.stencil_clear_tuning()
+    f = inputs.fields_sized(*dims, seed=109)
+    u, data, w = dev_fields(f, torch.float64, DEV)
+    u0 = u.tensor.clone()
+    scratch = fields.alloc(*dims, torch.float64, DEV, fill=0.0)
+    assert api.stencil_autotune_fields(u, data, w, scratch, dims, reps=2) > 0
+    assert torch.equal(u.tensor, u0)
+    ti, tj, col, order = api.stencil_tuning_lookup(torch.float64, api.OP_STEP, dims)
+    assert (ti, tj) in ((64, 4), (32, 8), (16, 16)) and order in (api.ORDER_XCD, api.ORDER_DISPATCH)
+    out = fields.alloc(*dims, torch.float64, DEV, fill=0.0)
+    api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ)
+    torch.cuda.synchronize()
+    ref, _, _ = orc.step(f.u, f.data, f.w, inputs.COEFF, inputs.DT_DZ)
+    assert rel_err(host(fields.interior(out, *dims)), ref[:, 2:-2, 2:-2]) <= 1e-12
+    api.stencil_clear_tuning()
 
 
 def test_empty_domains_leave_outputs_alone():

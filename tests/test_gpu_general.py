@@ -273,7 +273,7 @@ def test_autotune_hdiff_damping():
     ni, nj, nk = dims
     best = api.stencil_autotune(torch.float64, api.OP_HDIFF, dims, reps=2)
     assert best > 0
-    ti, tj, _ = api.stencil_tuning_lookup(torch.float64, api.OP_HDIFF, dims)
+    ti, tj, _, _ = api.stencil_tuning_lookup(torch.float64, api.OP_HDIFF, dims)
     assert (ti, tj) in ((64, 4), (32, 8), (16, 16))
     f = inputs.fields_sized(ni, nj, nk, seed=601)
     u = fields.from_padded(f.u, torch.float64, DEV)
