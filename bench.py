@@ -379,11 +379,12 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and kname in tr.get("kernels", {}):
-            traffic = round(tr["kernels"][kname]["bytes_per_launch"])
+        key = f"{kname} order={tuned['f64'][3]}"
+        if tr.get("kernel_hash") == kernel_hash() and key in tr.get("kernels", {}):
+            traffic = round(tr["kernels"][key]["bytes_per_launch"])
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": b64, "kernel": kname,
+            "algorithmic_bytes_per_launch": b64, "kernel": kname, "tile_order": tuned["f64"][3],
             "avg_launch_us": round(t_step * 1e6, 2)}
     out.update({
         "metric": METRIC, "value": round(npts * K / t_ev, 1), "unit": "grid points/s",
