@@ -334,7 +334,7 @@ int run_step_adjoint_batched(int n, const stencil_batch_adjoint_item* it, void* 
                                x.domain, x.coeff, 0.0, empty ? nullptr : x.mask);
     const int out_i = sizeof(T) == 4 ? kStripOut2 : kStripOut;  // FP32: two columns per lane
     A.tiles_i = (A.ni + 4 + out_i - 1) / out_i;
-    A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);  // strips
+    A.ntiles = A.tiles_i * ((A.nj + 4 + strip_rows<T>() - 1) / strip_rows<T>());  // strips
     hargs[e] = A;
   }
   auto groups = [](const AdjArgs<T>& A) { return (int64_t)(A.ntiles + kStripsPerWG - 1) / kStripsPerWG; };

@@ -15,10 +15,33 @@ constexpr int kWG = 256;          // threads per workgroup of every tile kernel
 // kSplitLongNT-column tiles
 constexpr int kSplitRegNkF64 = 96;
 constexpr int kSplitLongNT = 128;
-// the hdiff adjoint's strips: 64 lanes in i (60 outputs), kStripRows rows in j
+// the hdiff adjoint's strips: 64 lanes in i (60 outputs; FP32 124, two
+// columns per lane), strip_rows<T>() output rows in j, of whose
+// strip_rows<T>() + 4 input rows strip_pd<T>() are in flight ahead of their
+// use.  Measured on cold buffers (512x512x80 and 256x256x80): FP64 walks
+// 8 rows with the whole strip loaded at once, FP32 12 rows likewise.
 constexpr int kStripOut = 60;
-constexpr int kStripOut2 = 124;  // FP32: two columns per lane, 124 outputs
-constexpr int kStripRows = 16;
+constexpr int kStripOut2 = 124;
+#ifndef GT4MI_STRIP_ROWS_F64
+#define GT4MI_STRIP_ROWS_F64 8
+#endif
+#ifndef GT4MI_STRIP_PD_F64
+#define GT4MI_STRIP_PD_F64 12
+#endif
+#ifndef GT4MI_STRIP_ROWS_F32
+#define GT4MI_STRIP_ROWS_F32 12
+#endif
+#ifndef GT4MI_STRIP_PD_F32
+#define GT4MI_STRIP_PD_F32 16
+#endif
+template <typename T>
+constexpr int strip_rows() {
+  return sizeof(T) == 8 ? GT4MI_STRIP_ROWS_F64 : GT4MI_STRIP_ROWS_F32;
+}
+template <typename T>
+constexpr int strip_pd() {
+  return sizeof(T) == 8 ? GT4MI_STRIP_PD_F64 : GT4MI_STRIP_PD_F32;
+}
 constexpr int kStripsPerWG = kWG / 64;  // one strip per wave
 
 // ------------------------------------------------------------------ mask

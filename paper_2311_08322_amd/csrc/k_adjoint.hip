@@ -113,15 +113,15 @@ hipError_t launch_vadv_adjoint(AdjArgs<T> A, int impl_plain, T* ws_y, T* ws_c, h
   }
 }
 
-// strips of 60 x kStripRows outputs over the padded domain, four per
+// strips of 60 x strip_rows outputs over the padded domain, four per
 // workgroup, one level per grid row
 template <typename T>
 hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s) {
   const bool var = A.kappa != nullptr && A.lam != nullptr;  // per-point coefficient
   if constexpr (sizeof(T) == 4) {
-    // binary32: two columns per lane, strips of 124 x kStripRows outputs
+    // binary32: two columns per lane, strips of 124 x strip_rows outputs
     A.tiles_i = (A.ni + 4 + kStripOut2 - 1) / kStripOut2;
-    A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);
+    A.ntiles = A.tiles_i * ((A.nj + 4 + strip_rows<T>() - 1) / strip_rows<T>());
     const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
     if (var)
       hipLaunchKernelGGL(k_hdiff_adjoint_strip2<true>, grid, block, 0, s, A);
@@ -130,7 +130,7 @@ hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s) {
     return hipGetLastError();
   }
   A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;
-  A.ntiles = A.tiles_i * ((A.nj + 4 + kStripRows - 1) / kStripRows);
+  A.ntiles = A.tiles_i * ((A.nj + 4 + strip_rows<T>() - 1) / strip_rows<T>());
   const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
   if (var)
     hipLaunchKernelGGL((k_hdiff_adjoint_strip<T, true>), grid, block, 0, s, A);

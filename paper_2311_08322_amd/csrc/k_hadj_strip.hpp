@@ -25,8 +25,6 @@
 
 namespace gt4mi {
 
-constexpr int kStripPD = 4;  // rows in flight ahead of their use (PD)
-
 // The strip `t` (of A.tiles_i strips in i times the row blocks in j) at level k.
 template <typename T, int TJ, int PD, bool VAR>
 __device__ __forceinline__ void hdiff_adjoint_strip(const AdjArgs<T>& A, int t, int k) {
@@ -274,7 +272,7 @@ __global__ void __launch_bounds__(kWG) k_hdiff_adjoint_strip2(AdjArgs<float> A) 
   const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
                                                (int)(threadIdx.x >> 6));
   if (t >= A.ntiles) return;  // whole waves only: no barrier follows
-  hdiff_adjoint_strip2<kStripRows, kStripPD, VAR>(A, t, blockIdx.y);
+  hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), VAR>(A, t, blockIdx.y);
 }
 
 // One strip per wave, at one level per grid row.
@@ -284,7 +282,7 @@ __global__ void __launch_bounds__(kWG) k_hdiff_adjoint_strip(AdjArgs<T> A) {
   const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
                                                (int)(threadIdx.x >> 6));
   if (t >= A.ntiles) return;  // whole waves only: no barrier follows
-  hdiff_adjoint_strip<T, kStripRows, kStripPD, VAR>(A, t, blockIdx.y);
+  hdiff_adjoint_strip<T, strip_rows<T>(), strip_pd<T>(), VAR>(A, t, blockIdx.y);
 }
 
 }  // namespace gt4mi
