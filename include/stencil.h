@@ -346,7 +346,10 @@ size_t stencil_batch_adjoint_workspace_bytes(stencil_dtype dtype, int n,
 
 /* All n steps in one persistent launch (FP64: two, one for the fields with
  * columns of up to 80 levels, one for the longer ones, which run tiles of
- * tile_i x (128 / tile_i) columns).  The call sorts the items longest
+ * tile_i x (128 / tile_i) columns).  opts->tile_i, when set, is the tile of
+ * every field; when 0 each field takes its size class's tuned tile, or
+ * without one the width (64, 32 or 16) that leaves the fewest lanes idle
+ * on its ragged edges.  The call sorts the items longest
  * column first, writes the work list into `ws` with small copy kernels on
  * `stream` (stream-ordered, so the call can be captured into a graph), and
  * launches the kernel(s), whose workgroups pull (field, tile) work items from a
@@ -358,8 +361,8 @@ int stencil_step_batched(stencil_dtype dtype, int n, const stencil_batch_item* i
                          size_t ws_bytes, const stencil_options* opts, hipStream_t stream);
 /* The adjoints of a batch: one persistent launch for the column adjoints
  * (work items: field, 64x4 column tile), then one launch for the horizontal
- * gathers with a workgroup per work item (field, four 60x16 strips of the
- * padded domain, level).  ws as for the forward, sized by
+ * gathers with a workgroup per work item (field, four strips of the padded
+ * domain, level; a strip is 60 x 8 points in FP64, 124 x 12 in FP32).  ws as for the forward, sized by
  * stencil_batch_adjoint_workspace_bytes; opts->tile_i is not used. */
 int stencil_step_adjoint_batched(stencil_dtype dtype, int n,
                                  const stencil_batch_adjoint_item* items, void* ws,

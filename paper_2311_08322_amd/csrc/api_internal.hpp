@@ -90,8 +90,8 @@ int launch_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* item
                       const stencil_options* opts, hipStream_t stream);
 
 // tuning table (tune.cpp): tile, column store and tile order for (dtype, op,
-// size class)
-void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* tile_i, int32_t* tile_j,
+// size class); the defaults, and false, when the class has no entry
+bool tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* tile_i, int32_t* tile_j,
                 int32_t* column_store, int32_t* tile_order);
 
 }  // namespace gt4mi

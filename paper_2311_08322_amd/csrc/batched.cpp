@@ -40,21 +40,27 @@ Span mask_span(const void* mask, const int64_t* dom) {
   return Span{p, mask ? p + stencil_mask_bytes(dom) : p};
 }
 
-// The tile of a batched launch: the caller's, else the tuning table's entry
-// for the batch's largest field (one persistent kernel runs one tile shape).
-template <typename Item>
-int tile_i_of(const stencil_options* o, stencil_dtype dt, int op, int n, const Item* it) {
+// Tile width of one field of a forward batch (tiles of nt columns): the
+// caller's for every field, else the tuning table's entry for the field's
+// size class, else the width with the least cost: the lanes its tiles span
+// on the field (idle lanes on the ragged edges included) times the width's
+// cost per lane relative to 64-wide tiles, as the single-field step
+// measures it at 512x512x80 (FP64: 32 as fast, 16 6% slower; FP32: 32 8%,
+// 16 25% slower).  Ties go to the wider tile.
+int field_tile_i(const stencil_options* o, stencil_dtype dt, const int64_t* dom, int nt) {
   if (o && o->tile_i) return o->tile_i;
-  int best = -1;
-  int64_t most = -1;
-  for (int a = 0; a < n; ++a) {
-    const int64_t p = it[a].domain[0] * it[a].domain[1] * it[a].domain[2];
-    if (p > most) most = p, best = a;
-  }
-  if (best < 0) return 64;
   int32_t ti = 64, tj = 4, col = 0, ord = 0;
-  tuning_get(dt, op, it[best].domain, &ti, &tj, &col, &ord);
-  return (ti == 16 || ti == 32) ? ti : 64;
+  if (tuning_get(dt, STENCIL_OP_STEP, dom, &ti, &tj, &col, &ord)) return (ti == 16 || ti == 32) ? ti : 64;
+  static const int kPerMille[2][3] = {{1000, 1080, 1250}, {1000, 1000, 1060}};  // [FP32, FP64][64, 32, 16]
+  const int* fac = kPerMille[dt == STENCIL_F64 ? 1 : 0];
+  int best = 64;
+  int64_t least = -1;
+  for (int c = 0; c < 3; ++c) {
+    const int w = 64 >> c, h = nt / w;
+    const int64_t cost = (dom[0] + w - 1) / w * w * ((dom[1] + h - 1) / h * h) * fac[c];
+    if (least < 0 || cost < least) least = cost, best = w;
+  }
+  return best;
 }
 
 int check_batch_args(stencil_dtype dtype, int n, const void* items, const stencil_options* opts) {
@@ -213,7 +219,7 @@ void forward_groups(stencil_dtype dt, int n, const stencil_batch_item* it, int m
 }
 
 template <typename T>
-int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, hipStream_t s) {
+int run_step_batched(int n, const stencil_batch_item* it, void* ws, const stencil_options* opts, hipStream_t s) {
   constexpr stencil_dtype dt = sizeof(T) == 8 ? STENCIL_F64 : STENCIL_F32;
   const std::vector<int> ord = lpt_order(n, it, interior_work);
   if (ord.empty()) return ok();
@@ -222,7 +228,7 @@ int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, 
   // the long group first: its columns are the longest (longest work first)
   for (int g = 1; g >= 0; --g) {
     const bool long_tiles = g == 1;  // FP64 long columns: 128-column tiles
-    const int tile_j = (long_tiles ? kSplitLongNT : kWG) / tile_i;
+    const int nt = long_tiles ? kSplitLongNT : kWG;
     std::vector<StepArgs<T>> args;
     std::vector<int32_t> items;
     bool any_mask = false;
@@ -232,7 +238,9 @@ int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, 
       if (long_class(dt, x.domain) != (g == 1)) continue;
       StepArgs<T> A = step_args<T>(&x.u, &x.data, &x.w, const_cast<stencil_field*>(&x.out), x.domain, x.coeff,
                                    x.dt_dz, x.mask);
-      A.tiles_i = (A.ni + tile_i - 1) / tile_i;
+      A.tile_i = field_tile_i(opts, dt, x.domain, nt);
+      const int tile_j = nt / A.tile_i;
+      A.tiles_i = (A.ni + A.tile_i - 1) / A.tile_i;
       A.ntiles = A.tiles_i * ((A.nj + tile_j - 1) / tile_j);
       args.push_back(A);
       items.push_back(A.ntiles);
@@ -249,12 +257,12 @@ int run_step_batched(int n, const stencil_batch_item* it, void* ws, int tile_i, 
     const auto* ent = reinterpret_cast<const StepArgs<T>*>(base + off + table_head_bytes(m));
     if constexpr (sizeof(T) == 8) {
       if (long_tiles) {
-        TRY(hip_status(launch_step_batched_long<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched, long)"));
+        TRY(hip_status(launch_step_batched_long<T>(h, ent, (int)total, any_mask, s), "step (batched, long)"));
         off += (int64_t)blob.size();
         continue;
       }
     }
-    TRY(hip_status(launch_step_batched<T>(h, ent, (int)total, tile_i, any_mask, s), "step (batched)"));
+    TRY(hip_status(launch_step_batched<T>(h, ent, (int)total, any_mask, s), "step (batched)"));
     off += (int64_t)blob.size();
   }
   return ok();
@@ -372,9 +380,8 @@ int check_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items
 
 int launch_step_batch(stencil_dtype dtype, int n, const stencil_batch_item* items, void* ws,
                       const stencil_options* opts, hipStream_t stream) {
-  const int ti = tile_i_of(opts, dtype, STENCIL_OP_STEP, n, items);
-  return dtype == STENCIL_F64 ? run_step_batched<double>(n, items, ws, ti, stream)
-                              : run_step_batched<float>(n, items, ws, ti, stream);
+  return dtype == STENCIL_F64 ? run_step_batched<double>(n, items, ws, opts, stream)
+                              : run_step_batched<float>(n, items, ws, opts, stream);
 }
 
 }  // namespace gt4mi

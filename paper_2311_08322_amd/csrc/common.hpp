@@ -242,6 +242,7 @@ struct StepArgs {
   int64_t c_sj, c_sk;
   int form;  // 0: lap = 4u - sum of the neighbours; 1: the damping form, lap = sum - 4u
   int order;  // tile order of the two-ended step: 2 = dispatch order, else XCD runs
+  int tile_i;  // batched launches: the tile width of this item's field (64, 32 or 16)
 };
 
 // Sign that folds the damping form into the stated one: its Laplacian,

@@ -90,13 +90,34 @@ __device__ __forceinline__ int find_entry(const BatchHeader* h, int w) {
 }
 
 // ------------------------------------------------------------------ kernels
+// The fields of one launch may run different tile shapes (each field takes
+// the tile that wastes the fewest lanes on its ragged edges): the work item
+// runs the body of its field's tile, a uniform branch, in LDS shared by the
+// three shapes.
+template <typename T, int NT>
+union BatchSmem {
+  SplitSmem<T, 64, NT / 64> t64;
+  SplitSmem<T, 32, NT / 32> t32;
+  SplitSmem<T, 16, NT / 16> t16;
+};
+
+template <typename T, int NT, int NKH, int PD, bool MASK>
+__device__ __forceinline__ void batched_step_item(const StepArgs<T>& A, int tile, BatchSmem<T, NT>& sm) {
+  if (A.tile_i == 64)
+    step_split_tile<T, 64, NT / 64, NKH, PD, MASK, 1>(A, tile, sm.t64);
+  else if (A.tile_i == 32)
+    step_split_tile<T, 32, NT / 32, NKH, PD, MASK, 1>(A, tile, sm.t32);
+  else
+    step_split_tile<T, 16, NT / 16, NKH, PD, MASK, 1>(A, tile, sm.t16);
+}
+
 // Forward step, half-column register class NKH.  FP64 columns up to
 // kBatchedShortNk levels run in the 40-level class (the 48-level class
 // would spill beside the persistent loop's own registers), longer ones in
 // k_step_batched_long; FP32 columns all run in the 72-level class.
-template <typename T, int TI, int TJ, int NKH, bool MASK>
+template <typename T, int NKH, bool MASK>
 __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const StepArgs<T>* ent) {
-  __shared__ SplitSmem<T, TI, TJ> sm;
+  __shared__ BatchSmem<T, kWG> sm;
   __shared__ int slot;
   for (;;) {
     const int w = next_work(h, &slot);
@@ -104,18 +125,17 @@ __global__ void __launch_bounds__(2 * kWG) k_step_batched(BatchHeader* h, const 
     const int e = find_entry(h, w);
     const StepArgs<T> A = uniform_ld(ent + e);
     const int tile = w - uniform_ld(h->prefix() + e);
-    step_split_tile<T, TI, TJ, NKH, GT4MI_PD, MASK, 1>(A, tile, sm);
+    batched_step_item<T, kWG, NKH, GT4MI_PD, MASK>(A, tile, sm);
     __syncthreads();  // the LDS is reused by the next item
   }
 }
 
 #ifdef GT4MI_BATCHED_LONG
-// FP64 columns of kBatchedShortNk+1 .. 144 levels: TI x (kSplitLongNT / TI)
-// tiles of 256 lanes with e and f in VGPRs, as the single-field long form.
-template <typename T, int TI, bool MASK>
+// FP64 columns of kBatchedShortNk+1 .. 144 levels: tiles of kSplitLongNT
+// columns (256 lanes) with e and f in VGPRs, as the single-field long form.
+template <typename T, bool MASK>
 __global__ void __launch_bounds__(2 * kSplitLongNT) k_step_batched_long(BatchHeader* h, const StepArgs<T>* ent) {
-  constexpr int TJ = kSplitLongNT / TI;
-  __shared__ SplitSmem<T, TI, TJ> sm;
+  __shared__ BatchSmem<T, kSplitLongNT> sm;
   __shared__ int slot;
   for (;;) {
     const int w = next_work(h, &slot);
@@ -123,7 +143,7 @@ __global__ void __launch_bounds__(2 * kSplitLongNT) k_step_batched_long(BatchHea
     const int e = find_entry(h, w);
     const StepArgs<T> A = uniform_ld(ent + e);
     const int tile = w - uniform_ld(h->prefix() + e);
-    step_split_tile<T, TI, TJ, 72, GT4MI_PD, MASK, 1>(A, tile, sm);
+    batched_step_item<T, kSplitLongNT, kSplitStagedNkhF64, GT4MI_PD_LONG, MASK>(A, tile, sm);
     __syncthreads();
   }
 }
@@ -173,39 +193,26 @@ __global__ void __launch_bounds__(kWG) k_hadj_batched(const BatchHeader* h, cons
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename T, int NKH>
-hipError_t launch_step_batched_class(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                                     hipStream_t s) {
+template <typename T>
+hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, bool mask, hipStream_t s) {
+  constexpr int NKH = sizeof(T) == 8 ? kBatchedShortNk / 2 : 72;
   auto go = [&](auto kernel) {
     const int grid = persistent_grid(kernel, 2 * kWG, total);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(2 * kWG), 0, s, h, ent);
     return hipGetLastError();
   };
-  if (tile_i == 64)
-    return mask ? go(k_step_batched<T, 64, 4, NKH, true>) : go(k_step_batched<T, 64, 4, NKH, false>);
-  if (tile_i == 32)
-    return mask ? go(k_step_batched<T, 32, 8, NKH, true>) : go(k_step_batched<T, 32, 8, NKH, false>);
-  return mask ? go(k_step_batched<T, 16, 16, NKH, true>) : go(k_step_batched<T, 16, 16, NKH, false>);
-}
-
-template <typename T>
-hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                               hipStream_t s) {
-  return launch_step_batched_class<T, sizeof(T) == 8 ? kBatchedShortNk / 2 : 72>(h, ent, total, tile_i, mask, s);
+  return mask ? go(k_step_batched<T, NKH, true>) : go(k_step_batched<T, NKH, false>);
 }
 
 #ifdef GT4MI_BATCHED_LONG
 template <typename T>
-hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                                    hipStream_t s) {
+hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, bool mask, hipStream_t s) {
   auto go = [&](auto kernel) {
     const int grid = persistent_grid(kernel, 2 * kSplitLongNT, total);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(2 * kSplitLongNT), 0, s, h, ent);
     return hipGetLastError();
   };
-  if (tile_i == 64) return mask ? go(k_step_batched_long<T, 64, true>) : go(k_step_batched_long<T, 64, false>);
-  if (tile_i == 32) return mask ? go(k_step_batched_long<T, 32, true>) : go(k_step_batched_long<T, 32, false>);
-  return mask ? go(k_step_batched_long<T, 16, true>) : go(k_step_batched_long<T, 16, false>);
+  return mask ? go(k_step_batched_long<T, true>) : go(k_step_batched_long<T, false>);
 }
 #endif
 
@@ -226,12 +233,11 @@ hipError_t launch_hadj_batched(BatchHeader* h, const AdjArgs<T>* ent, int total,
 // one object per element type (-DGT4MI_T=float|double); the float one also
 // holds the table upload (-DGT4MI_UPLOAD), the double one the long-column
 // forward (-DGT4MI_BATCHED_LONG)
-template hipError_t launch_step_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool, hipStream_t);
+template hipError_t launch_step_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, bool, hipStream_t);
 template hipError_t launch_vadj_batched<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, hipStream_t);
 template hipError_t launch_hadj_batched<GT4MI_T>(BatchHeader*, const AdjArgs<GT4MI_T>*, int, hipStream_t);
 #ifdef GT4MI_BATCHED_LONG
-template hipError_t launch_step_batched_long<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, int, bool,
-                                                      hipStream_t);
+template hipError_t launch_step_batched_long<GT4MI_T>(BatchHeader*, const StepArgs<GT4MI_T>*, int, bool, hipStream_t);
 #endif
 
 }  // namespace gt4mi

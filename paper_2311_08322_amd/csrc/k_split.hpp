@@ -265,6 +265,11 @@ __global__ void __launch_bounds__(2 * TI * TJ) k_step_split(StepArgs<T> A) {
 // stage f in the output, as the batched kernel does beyond 80 levels.
 #define GT4MI_NKH_CLASSES(X) X(16) X(24) X(40) X(48) X(56) X(80)
 constexpr int kSplitStagedNkhF64 = 72;
+// Levels loaded ahead in the long FP64 form.  It runs one wave per SIMD, so
+// each wave has to keep more loads in flight than in the two-wave classes.
+#ifndef GT4MI_PD_LONG
+#define GT4MI_PD_LONG 4
+#endif
 
 template <typename T>
 constexpr int split_max_nk() {
@@ -306,9 +311,9 @@ hipError_t launch_split_long(const StepArgs<T>& A, hipStream_t s) {
   const dim3 grid(A.ntiles), block(2 * TI * TJ);
   if (A.nk - A.nk / 2 > kSplitStagedNkhF64) return hipErrorInvalidValue;
   if (A.mask)
-    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD, true, 1, false>), grid, block, 0, s, A);
+    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD_LONG, true, 1, false>), grid, block, 0, s, A);
   else
-    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD, false, 1, false>), grid, block, 0, s, A);
+    hipLaunchKernelGGL((k_step_split<T, TI, TJ, kSplitStagedNkhF64, GT4MI_PD_LONG, false, 1, false>), grid, block, 0, s, A);
   return hipGetLastError();
 }
 

@@ -82,15 +82,14 @@ constexpr int kMaxBatchedNk = 144;
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 // FP64 columns of up to kBatchedShortNk levels run in the 40-level
 // half-column class, longer ones in launch_step_batched_long; FP32 columns
-// all run in the 72-level class.
+// all run in the 72-level class.  Each argument block names its field's
+// tile width (StepArgs::tile_i: tiles of kWG columns, kSplitLongNT in the
+// long launch).
 constexpr int kBatchedShortNk = 80;
 template <typename T>
-hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                               hipStream_t s);
-// FP64 columns longer than kSplitRegNkF64 (tiles of kSplitLongNT columns)
+hipError_t launch_step_batched(BatchHeader* h, const StepArgs<T>* ent, int total, bool mask, hipStream_t s);
 template <typename T>
-hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, int tile_i, bool mask,
-                                    hipStream_t s);
+hipError_t launch_step_batched_long(BatchHeader* h, const StepArgs<T>* ent, int total, bool mask, hipStream_t s);
 template <typename T>
 hipError_t launch_vadj_batched(BatchHeader* h, const StepArgs<T>* ent, int total, hipStream_t s);
 template <typename T>

@@ -45,7 +45,7 @@ static int area_class(int64_t ni, int64_t nj) {
   return a < 128 * 128 ? 0 : (a < 256 * 256 ? 1 : 2);
 }
 
-void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32_t* tj, int32_t* col,
+bool tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32_t* tj, int32_t* col,
                 int32_t* order) {
   TuneKey k{(int)dt, op, nk_class(dom[2]), area_class(dom[0], dom[1])};
   std::lock_guard<std::mutex> lk(g_mu);
@@ -55,12 +55,13 @@ void tuning_get(stencil_dtype dt, int op, const int64_t* dom, int32_t* ti, int32
     *tj = it->second.tile_j;
     *col = it->second.col;
     *order = it->second.order;
-  } else {
-    *ti = 64;
-    *tj = 4;
-    *col = STENCIL_COLUMN_AUTO;
-    *order = STENCIL_ORDER_XCD;
+    return true;
   }
+  *ti = 64;
+  *tj = 4;
+  *col = STENCIL_COLUMN_AUTO;
+  *order = STENCIL_ORDER_XCD;
+  return false;
 }
 
 }  // namespace gt4mi

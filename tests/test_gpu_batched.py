@@ -117,6 +117,46 @@ def test_forward_batch_vs_separate(batch, dtype, tile):
         assert torch.equal(a["mask"], b["mask"]), a["domain"]
 
 
+def _least_cost_tile(ni, nj, nt, dtype):
+    """The tile width an automatic batch gives a field without a tuned entry:
+    the lanes its tiles span (idle edge lanes included) times a per-width
+    cost (relative to 64-wide tiles), least first, ties to the wider."""
+    fac = {64: 1000, 32: 1000, 16: 1060} if dtype == torch.float64 else {64: 1000, 32: 1080, 16: 1250}
+    best, least = 64, None
+    for w in (64, 32, 16):
+        h = nt // w
+        cost = -(-ni // w) * w * (-(-nj // h) * h) * fac[w]
+        if least is None or cost < least:
+            best, least = w, cost
+    return best
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=IDS)
+def test_forward_batch_per_field_tiles(batch, dtype):
+    """Without a tile option each field runs its own tile shape in the same
+    launch; every field equals its separate launch with that tile."""
+    print(f"batched forward, per-field tiles, {dtype}", flush=True)
+    api.stencil_clear_tuning()  # no tuned entries: the cost rule decides
+    items = _items(batch, dtype)
+    _run_batched(items, dtype)
+    sep = _items(batch, dtype)
+    shapes = set()
+    for it in sep:
+        ni, nj, nk = it["domain"]
+        nt = 128 if dtype == torch.float64 and nk > 80 else 256
+        tile = _least_cost_tile(ni, nj, nt, dtype)
+        shapes.add(tile)
+        o = api.Options(tile_i=tile)
+        o.workspace = fields.workspace(api.OP_STEP, dtype, it["domain"], o)
+        api.stencil_step(it["u"], it["data"], it["w"], it["out"], it["domain"], inputs.COEFF, inputs.DT_DZ,
+                         mask=it["mask"], opts=o)
+    torch.cuda.synchronize()
+    assert len(shapes) > 1  # the workload mixes tile shapes in one launch
+    for a, b in zip(items, sep):
+        assert torch.equal(_interior(a), _interior(b)), a["domain"]
+        assert torch.equal(a["mask"], b["mask"]), a["domain"]
+
+
 def _adjoint_items(items, dtype, with_dbar):
     adj = []
     for n, it in enumerate(items):
