@@ -53,6 +53,14 @@ def adjoint_bytes(ni, nj, nk, es) -> int:
         nk * nj * ((ni + 63) // 64) * 16 + nk * (ni + nj)
 
 
+def adjoint_kernel_bytes(ni, nj, nk, es) -> int:
+    """Algorithmic bytes of the two kernels the step adjoint runs: the
+    column adjoint (read x_bar and w, write lambda = data_bar) and the
+    gather (read lambda and the mask, write u_bar): the step adjoint's
+    bytes plus lambda read back once."""
+    return adjoint_bytes(ni, nj, nk, es) + es * nk * ni * nj
+
+
 def stream_mix_bandwidth(mib: int, reps: int) -> dict:
     """One elementwise pass that reads three arrays and writes a fourth
     (torch.addcmul over `mib` MiB each): plain streaming with the fused
@@ -445,6 +453,7 @@ def main():
         out["adjoint"] = {"ratio_adj_over_fwd": round(t_adj / t_fwd, 3), "fwd_mask_ms": round(t_fwd * 1e3, 4),
                           "adj_ms": round(t_adj * 1e3, 4), "adj_gbs": round(ab / t_adj / 1e9, 1),
                           "adj_frac": round(ab / t_adj / 1e9 / PEAK_GBS, 4),
+                          "adj_kernels_gbs": round(adjoint_kernel_bytes(ni, nj, nk, 8) / t_adj / 1e9, 1),
                           "fwd_mask_gbs": round(step_bytes(ni, nj, nk, 8, True) / t_fwd / 1e9, 1)}
         # ---------------------------- the adjoint workload 256x256x80, rotating sets
         # one set (about 170 MB in FP64) fits the 256 MB last-level cache, so
