@@ -275,4 +275,13 @@ struct AdjArgs {
   int64_t c_sj, c_sk;
 };
 
+// ni is even and lambda's rows keep 8-byte alignment (base, row and level
+// strides): the binary32 gather then reads a lane's two columns, an even and
+// an odd one, with one load
+template <typename T>
+__host__ __device__ inline bool lambda_pairs_ok(const AdjArgs<T>& A) {
+  return A.ni % 2 == 0 && reinterpret_cast<uintptr_t>(A.lam) % 8 == 0 &&
+         (A.l_sj * (int64_t)sizeof(T)) % 8 == 0 && (A.l_sk * (int64_t)sizeof(T)) % 8 == 0;
+}
+
 }  // namespace gt4mi

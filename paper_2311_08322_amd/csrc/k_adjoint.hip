@@ -123,10 +123,15 @@ hipError_t launch_hdiff_adjoint(AdjArgs<T> A, hipStream_t s) {
     A.tiles_i = (A.ni + 4 + kStripOut2 - 1) / kStripOut2;
     A.ntiles = A.tiles_i * ((A.nj + 4 + strip_rows<T>() - 1) / strip_rows<T>());
     const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
-    if (var)
-      hipLaunchKernelGGL(k_hdiff_adjoint_strip2<true>, grid, block, 0, s, A);
+    const bool pair = lambda_pairs_ok(A);
+    if (var && pair)
+      hipLaunchKernelGGL((k_hdiff_adjoint_strip2<true, true>), grid, block, 0, s, A);
+    else if (var)
+      hipLaunchKernelGGL((k_hdiff_adjoint_strip2<true, false>), grid, block, 0, s, A);
+    else if (pair)
+      hipLaunchKernelGGL((k_hdiff_adjoint_strip2<false, true>), grid, block, 0, s, A);
     else
-      hipLaunchKernelGGL(k_hdiff_adjoint_strip2<false>, grid, block, 0, s, A);
+      hipLaunchKernelGGL((k_hdiff_adjoint_strip2<false, false>), grid, block, 0, s, A);
     return hipGetLastError();
   }
   A.tiles_i = (A.ni + 4 + kStripOut - 1) / kStripOut;

@@ -186,7 +186,12 @@ __global__ void __launch_bounds__(kWG) k_hadj_batched(const BatchHeader* h, cons
   const int t = __builtin_amdgcn_readfirstlane(g * kStripsPerWG + (int)(threadIdx.x >> 6));
   if (t < A.ntiles) {
     if constexpr (sizeof(T) == 4)
-      hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), false>(A, t, k);  // two columns per lane
+    {  // two columns per lane, read in pairs where the item's lambda allows (uniform)
+      if (lambda_pairs_ok(A))
+        hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), false, true>(A, t, k);
+      else
+        hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), false, false>(A, t, k);
+    }
     else
       hdiff_adjoint_strip<T, strip_rows<T>(), strip_pd<T>(), false>(A, t, k);
   }

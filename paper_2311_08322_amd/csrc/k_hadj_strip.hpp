@@ -141,9 +141,10 @@ __device__ __forceinline__ void hdiff_adjoint_strip(const AdjArgs<T>& A, int t, 
 // neighbour of a and the west neighbour of b are in the lane itself, so a
 // row needs half the shifts, and both columns' limiter bits sit in one 32-bit
 // word of each mask plane.  Same values as hdiff_adjoint_strip, in the same
-// order of operations.
-
-template <int TJ, int PD, bool VAR>
+// order of operations.  PAIR: ni is even and lambda's rows keep 8-byte
+// alignment (the caller checks: lambda_pairs_ok), so a lane reads its two
+// columns with one 8-byte load, one request per cache line instead of two.
+template <int TJ, int PD, bool VAR, bool PAIR = false>
 __device__ __forceinline__ void hdiff_adjoint_strip2(const AdjArgs<float>& A, int t, int k) {
   static_assert((TJ + 4) % PD == 0, "the row walk is unrolled by the prefetch depth");
   using T = float;
@@ -171,6 +172,9 @@ __device__ __forceinline__ void hdiff_adjoint_strip2(const AdjArgs<float>& A, in
   const char* ybase = mbase + A.ml.y_off + (int64_t)k * plane_xy;
   const uint32_t la_off = ia >= 0 ? (uint32_t)ia * S : kOffNone;  // window: ni
   const uint32_t lb_off = ib >= 0 ? (uint32_t)ib * S : kOffNone;
+  // PAIR: both columns in one load (ia even and ni even: a inside the row
+  // means b inside too; ia < 0 means both outside)
+  [[maybe_unused]] const uint32_t lp_off = (ia >= 0 && ia < ni) ? (uint32_t)ia * S : kOffNone;
   // the 32-bit word of a mask row that holds bits a and b (a even)
   const uint32_t m_off = (aI && has_mask) ? (uint32_t)((ia >> 6) * 8 + ((ia >> 5) & 1) * 4) : kOffNone;
   const int mbit = ia & 31;
@@ -197,8 +201,17 @@ __device__ __forceinline__ void hdiff_adjoint_strip2(const AdjArgs<float>& A, in
   uint32_t pmx[PD], pmy[PD];
   auto issue = [&](int r, int s) {
     const auto rl = row_rsrc(lbase, A.l_sj * S, r, nj, (uint32_t)ni * S);
-    pla[s] = buf_ld(rl, la_off, T());
-    plb[s] = buf_ld(rl, lb_off, T());
+    if constexpr (PAIR) {
+      // the 8 bytes are taken apart as a float vector: element access on the
+      // builtin's integer vector narrowed the load to its first word here
+      typedef float f32x2_t __attribute__((ext_vector_type(2)));
+      const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rl, lp_off, 0, 0));
+      pla[s] = v[0];
+      plb[s] = v[1];
+    } else {
+      pla[s] = buf_ld(rl, la_off, T());
+      plb[s] = buf_ld(rl, lb_off, T());
+    }
     if constexpr (VAR) {
       const auto rk = row_rsrc(kbase, A.c_sj * S, r, nj, (uint32_t)ni * S);
       pka[s] = buf_ld(rk, la_off, T());
@@ -267,12 +280,12 @@ __device__ __forceinline__ void hdiff_adjoint_strip2(const AdjArgs<float>& A, in
   for (int s = 0; s < PD; ++s) step(n + s, s, false);
 }
 
-template <bool VAR>
+template <bool VAR, bool PAIR>
 __global__ void __launch_bounds__(kWG) k_hdiff_adjoint_strip2(AdjArgs<float> A) {
   const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
                                                (int)(threadIdx.x >> 6));
   if (t >= A.ntiles) return;  // whole waves only: no barrier follows
-  hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), VAR>(A, t, blockIdx.y);
+  hdiff_adjoint_strip2<strip_rows<float>(), strip_pd<float>(), VAR, PAIR>(A, t, blockIdx.y);
 }
 
 // One strip per wave, at one level per grid row.

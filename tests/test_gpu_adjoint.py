@@ -293,3 +293,42 @@ def test_hdiff_adjoint_strip_edges(dims, field, dtype):
     outside = torch.ones_like(before, dtype=torch.bool)
     outside[ok:ok + nk, oj - 2:oj + nj + 2, oi - 2:oi + ni + 2] = False
     assert torch.equal(ub.tensor[outside], before[outside])
+
+
+LAMBDA_LAYOUT_CASES = [(67, 45, 7), (64, 20, 3), (125, 9, 2), (1, 5, 2), (248, 13, 2)]
+
+
+@pytest.mark.parametrize("dims", LAMBDA_LAYOUT_CASES, ids=lambda d: "x".join(map(str, d)))
+def test_hdiff_adjoint_f32_lambda_layouts(dims):
+    """The binary32 gather reads a lane's two columns of lambda with one load
+    where ni is even and lambda's rows keep 8-byte alignment, column by
+    column otherwise (odd ni, odd pitch, a base 4 bytes off): every layout
+    gives the same bits, and the oracle's values."""
+    ni, nj, nk = dims
+    print(f"hdiff adjoint FP32 lambda layouts {dims}", flush=True)
+    dt = torch.float32
+    f = inputs.fields_sized(ni, nj, nk, seed=205)
+    u = fields.from_padded(f.u, dt, DEV)
+    out = fields.alloc(ni, nj, nk, dt, DEV, fill=0.0)
+    mask = fields.mask_tensor(dims, DEV)
+    api.stencil_hdiff(u, out, dims, inputs.COEFF, mask=mask)
+    lam = inputs.cotangent(ni, nj, nk)
+    # 8-byte aligned rows; an odd pitch (ni + 1 for even ni); a base 4 bytes off
+    pitch = ni if ni % 2 else ni + 1
+    t_odd = torch.zeros((nk, nj, pitch), dtype=dt, device=DEV)
+    t_odd[:, :, :ni] = torch.as_tensor(lam).to(dt)
+    t_off = torch.zeros((nk, nj, ni + 2), dtype=dt, device=DEV)
+    t_off[:, :, 1:ni + 1] = torch.as_tensor(lam).to(dt)
+    layouts = {"aligned": fields.from_interior(lam, dt, DEV),
+               "odd_pitch": api.Field(t_odd, (0, 0, 0)),
+               "offset": api.Field(t_off, (1, 0, 0))}
+    res = {}
+    for name, lb in layouts.items():
+        ub = fields.alloc(ni, nj, nk, dt, DEV, fill=9.0)
+        api.stencil_hdiff_adjoint(lb, mask, ub, dims, inputs.COEFF)
+        torch.cuda.synchronize()
+        res[name] = fields.padded(ub, ni, nj, nk).clone()
+    assert torch.equal(res["aligned"], res["odd_pitch"]) and torch.equal(res["aligned"], res["offset"])
+    mx, my = orc.hdiff_masks(round_f32(f.u), decide_f32=True)
+    ubr = orc.hdiff_adjoint(round_f32(lam), mx, my, c_scalar(inputs.COEFF, dt))
+    assert rel_err(host(res["aligned"]), ubr) <= TOL[dt]
