@@ -19,7 +19,10 @@ hipError_t launch_hdiff_fused(StepArgs<T> A, int tile_i, hipStream_t s) {
       A.tiles_i = (A.ni + kHStripOut2 - 1) / kHStripOut2;
       A.ntiles = A.tiles_i * ((A.nj + kHStripRows - 1) / kHStripRows);
       const dim3 grid((A.ntiles + kStripsPerWG - 1) / kStripsPerWG, A.nk), block(kWG);
-      hipLaunchKernelGGL(k_hdiff_strip2, grid, block, 0, s, A);
+      if (hdiff_pairs_ok(A))
+        hipLaunchKernelGGL(k_hdiff_strip2<true>, grid, block, 0, s, A);
+      else
+        hipLaunchKernelGGL(k_hdiff_strip2<false>, grid, block, 0, s, A);
       return hipGetLastError();
     }
     A.tiles_i = (A.ni + kHStripOut - 1) / kHStripOut;

@@ -136,7 +136,10 @@ __device__ __forceinline__ uint32_t spread4(uint32_t v) {
   return (v & 1u) | ((v & 2u) << 1) | ((v & 4u) << 2) | ((v & 8u) << 3);
 }
 
-template <int TJ, int PD>
+// PAIR: ni is even and the rows of u (from its padded corner) and out keep
+// 8-byte alignment, so a lane reads and writes its two columns with one
+// 8-byte access each (one request per cache line instead of two).
+template <int TJ, int PD, bool PAIR = false>
 __device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, int k) {
   static_assert((TJ + 4) % PD == 0, "the row walk is unrolled by the prefetch depth");
   using T = float;
@@ -161,6 +164,10 @@ __device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, in
   const uint32_t ub_off = (ib >= -2 && ib < ni + 2) ? (uint32_t)(ib + 2) * S : kOffNone;
   const uint32_t oa_off = owna ? (uint32_t)ia * S : kOffNone;  // window: ni
   const uint32_t ob_off = ownb ? (uint32_t)ib * S : kOffNone;
+  // PAIR (ni even, ia even): a inside its window means b inside too
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  [[maybe_unused]] const uint32_t up_off = ua_off;
+  [[maybe_unused]] const uint32_t op_off = oa_off;
   // limiter bytes: one descriptor over the whole mask (below 4 GiB), lanes
   // 0..14 the x bytes of a row, lanes 16..30 its y bytes
   const auto rm = make_rsrc(A.mask, has_mask ? (uint32_t)A.ml.total : 0u);
@@ -178,8 +185,16 @@ __device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, in
   constexpr int NR = TJ + 4;
   auto issue = [&](int r, int s) {
     const auto ru = row_rsrc(ubase, A.u_sj * S, r + 2, nj + 4, (uint32_t)(ni + 4) * S);
-    pa[s] = buf_ld(ru, ua_off, T());
-    pb[s] = buf_ld(ru, ub_off, T());
+    if constexpr (PAIR) {
+      // taken apart as a float vector: element access on the builtin's
+      // integer vector narrowed the load to its first word
+      const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(ru, up_off, 0, 0));
+      pa[s] = v[0];
+      pb[s] = v[1];
+    } else {
+      pa[s] = buf_ld(ru, ua_off, T());
+      pb[s] = buf_ld(ru, ub_off, T());
+    }
   };
 
   T u1a = 0, u1b = 0, u2a = 0, u2b = 0, lap2a = 0, lap2b = 0, Fx2a = 0, Fx2b = 0, Fy3a = 0, Fy3b = 0;
@@ -207,8 +222,13 @@ __device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, in
     const bool qrow = q >= j0 && q < j0 + TJ;  // uniform
     if (qrow) {
       const auto ro = row_rsrc(obase, A.o_sj * S, q, nj, (uint32_t)ni * S);
-      buf_st(ro, oa_off, va);
-      buf_st(ro, ob_off, vb);
+      if constexpr (PAIR) {
+        const f32x2_t v = {va, vb};
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), ro, op_off, 0, 0);
+      } else {
+        buf_st(ro, oa_off, va);
+        buf_st(ro, ob_off, vb);
+      }
     }
     if (has_mask) {
       const int rx = R - 1;
@@ -247,11 +267,21 @@ __device__ __forceinline__ void hdiff_strip2(const StepArgs<float>& A, int t, in
   for (int s = 0; s < PD; ++s) step(n + s, s, false);
 }
 
+template <bool PAIR>
 __global__ void __launch_bounds__(kWG) k_hdiff_strip2(StepArgs<float> A) {
   const int t = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * kStripsPerWG +
                                                (int)(threadIdx.x >> 6));
   if (t >= A.ntiles) return;  // whole waves only: no barrier follows
-  hdiff_strip2<kHStripRows, kHStripPD>(A, t, blockIdx.y);
+  hdiff_strip2<kHStripRows, kHStripPD, PAIR>(A, t, blockIdx.y);
+}
+
+// ni is even and the rows of u (from its padded corner) and out keep 8-byte
+// alignment: the binary32 row walk then reads and writes column pairs
+inline bool hdiff_pairs_ok(const StepArgs<float>& A) {
+  const auto al = [](const void* p, int64_t sj, int64_t sk) {
+    return reinterpret_cast<uintptr_t>(p) % 8 == 0 && (sj * 4) % 8 == 0 && (sk * 4) % 8 == 0;
+  };
+  return A.ni % 2 == 0 && al(A.u - 2 - 2 * A.u_sj, A.u_sj, A.u_sk) && al(A.out, A.o_sj, A.o_sk);
 }
 
 // One strip per wave, at one level per grid row.

@@ -174,6 +174,41 @@ def test_step_unaligned_and_strided_layouts():
     assert rel_err(host(fields.interior(out, ni, nj, nk)), ref[:, 2:-2, 2:-2]) <= 1e-12
 
 
+@pytest.mark.parametrize("dims", [(64, 20, 3), (248, 13, 2), (67, 9, 2), (2, 5, 2)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_hdiff_f32_layouts(dims):
+    """The binary32 row walk reads and writes column pairs with one 8-byte
+    access where ni is even and the rows of u and out keep 8-byte alignment,
+    column by column otherwise (odd ni, u 4 bytes off, out with an odd
+    pitch): the same bits, the same masks, and the oracle's values."""
+    ni, nj, nk = dims
+    print(f"hdiff FP32 layouts {dims}", flush=True)
+    dt = torch.float32
+    f = inputs.fields_sized(ni, nj, nk, seed=106)
+    ua = fields.from_padded(f.u, dt, DEV)
+    big = torch.zeros((nk, nj + 4, ni + 5), dtype=dt, device=DEV)
+    big[:, :, 1:ni + 5] = torch.as_tensor(f.u).to(dt)
+    uo = api.Field(big, (3, 2, 0))  # the padded corner 4 bytes past an 8-byte boundary
+    runs = {}
+    for name, u, aligned_out in (("aligned", ua, True), ("u_off", uo, True), ("out_odd", ua, False)):
+        if aligned_out:
+            out = fields.alloc(ni, nj, nk, dt, DEV, fill=0.0)
+        else:
+            pitch = ni + 5 if (ni + 4) % 2 == 0 else ni + 4
+            out = api.Field(torch.zeros((nk, nj + 4, pitch), dtype=dt, device=DEV), (2, 2, 0))
+        mask = fields.mask_tensor(dims, DEV)
+        api.stencil_hdiff(u, out, dims, inputs.COEFF, mask=mask)
+        torch.cuda.synchronize()
+        runs[name] = (fields.interior(out, ni, nj, nk).clone(), mask.clone())
+    for name in ("u_off", "out_odd"):
+        assert torch.equal(runs[name][0], runs["aligned"][0]), name
+        assert torch.equal(runs[name][1], runs["aligned"][1]), name
+    ref, mx, my = orc.hdiff(round_f32(f.u), c_scalar(inputs.COEFF, dt), decide_f32=True)
+    assert rel_err(host(runs["aligned"][0]), ref[:, 2:-2, 2:-2]) <= TOL[dt]
+    gx, gy = unpack_mask(runs["aligned"][1], ni, nj, nk)
+    assert np.array_equal(gx, mx) and np.array_equal(gy, my)
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 @pytest.mark.parametrize("wl", [inputs.STEP_256, inputs.STEP_512], ids=["256", "512"])
 def test_step_full_size(wl, dtype):
