@@ -43,14 +43,22 @@ class Field:
     origin: Sequence[int] = (0, 0, 0)
 
     def c(self) -> _lib.StencilField:
+        """The C descriptor, rebuilt only when the tensor's storage, shape,
+        strides or the origin changed (building it costs a few microseconds
+        per field, a noticeable part of a call on a small domain)."""
         t = self.tensor
+        key = (t.data_ptr(), t.shape, t.stride(), tuple(self.origin))
+        cached = self.__dict__.get("_c")
+        if cached is not None and cached[0] == key:
+            return cached[1]
         if t.dim() != 3:
             raise ValueError("a field tensor is 3-D, laid out (k, j, i)")
         f = _lib.StencilField()
-        f.data = t.data_ptr()
+        f.data = key[0]
         f.shape = _lib.I64x3(t.shape[2], t.shape[1], t.shape[0])
         f.stride = _lib.I64x3(t.stride(2), t.stride(1), t.stride(0))
         f.origin = _lib.I64x3(*[int(x) for x in self.origin])
+        self.__dict__["_c"] = (key, f)
         return f
 
     @property

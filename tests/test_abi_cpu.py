@@ -548,3 +548,27 @@ def test_generalised_diffusion_validation(L):
     bad = _lib.StencilOptions()
     bad.hdiff_form = -1
     assert L.stencil_coeff_field_adjoint(1, b(u), b(lam), b(kb), d, b(bad), None) == code("STENCIL_E_ARG")
+
+
+def test_field_descriptor_follows_the_tensor():
+    """The binding keeps a field's C descriptor between calls and rebuilds it
+    whenever the storage, shape, strides or origin change."""
+    import torch
+
+    from paper_2311_08322_amd import api
+    t = torch.zeros((3, 8, 10), dtype=torch.float64)
+    f = api.Field(t, (2, 2, 0))
+    a = f.c()
+    assert f.c() is a  # unchanged: the same descriptor
+    assert (a.data, list(a.shape), list(a.stride), list(a.origin)) == (t.data_ptr(), [10, 8, 3], [1, 10, 80], [2, 2, 0])
+    f.origin = (3, 2, 1)
+    assert list(f.c().origin) == [3, 2, 1]
+    u = torch.zeros((3, 8, 12), dtype=torch.float64)[:, :, 1:11]
+    f.tensor = u
+    b = f.c()
+    assert (b.data, list(b.shape), list(b.stride)) == (u.data_ptr(), [10, 8, 3], [1, 12, 96])
+    t2 = torch.zeros((3, 8, 10), dtype=torch.float64)
+    f.tensor = t2
+    t2.resize_(4, 9, 10)  # the same tensor object, new storage and shape
+    c = f.c()
+    assert (c.data, list(c.shape), list(c.stride)) == (t2.data_ptr(), [10, 9, 4], [1, 10, 90])
