@@ -412,10 +412,11 @@ def main():
         # replays, and every tile the tuner may pick gets measured
         u_a, u_b, data, w = mkfields(torch.float64)
         for tile in (64, 32, 16):
-            for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
-                o = api.Options(tile_i=tile, tile_j=256 // tile, column_store=api.COLUMN_SPLIT, tile_order=order)
-                for n in range(3):
-                    api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
+            for nt in (256, 128):  # both workgroup sizes
+                for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
+                    o = api.Options(tile_i=tile, tile_j=nt // tile, column_store=api.COLUMN_SPLIT, tile_order=order)
+                    for n in range(3):
+                        api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
         if args.with_adjoint:
             # the step adjoint (column adjoint + gather) on the forward's mask
             mask = fields.mask_tensor(dims, dev)

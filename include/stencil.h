@@ -143,11 +143,16 @@ typedef struct {
   int32_t impl;         /* stencil_impl */
   int32_t tile_i;       /* horizontal tile of the fused forward kernels (step, */
   int32_t tile_j;       /*   batched step, hdiff of the generalised diffusion);
-                           0 = tuned; supported: 64x4, 32x8, 16x16.  FP64
-                           columns of 97..144 levels in the two-ended step run
-                           tile_i x (128 / tile_i) tiles.  The stated hdiff
-                           and the adjoints' gather walk fixed strips and
-                           ignore it (the value is still validated). */
+                           0 = tuned; supported: 64x4, 32x8, 16x16 (256
+                           columns) and, for the two-ended step only (column
+                           store SPLIT, else STENCIL_E_UNSUPPORTED), 64x2,
+                           32x4, 16x8 (128 columns: 256-lane workgroups);
+                           tile_j = 0 with tile_i set means the 256-column
+                           tile.  FP64 columns of 97..144 levels in the
+                           two-ended step run tile_i x (128 / tile_i) tiles.
+                           Other calls use the tile's width only; the stated
+                           hdiff and the adjoints' gather walk fixed strips
+                           and ignore it (the value is still validated). */
   int32_t column_store; /* stencil_column_store */
   void* workspace;      /* device memory for STENCIL_IMPL_PLAIN temporaries */
   size_t workspace_bytes;
@@ -403,7 +408,8 @@ int stencil_graph_destroy(stencil_graph* graph);
 
 /* ---------------------------------------------------------------- tuning */
 /* Times every tile candidate of `op` (STENCIL_OP_STEP: tile x column store,
- * and both tile orders for the two-ended column store; or STENCIL_OP_HDIFF,
+ * and for the two-ended column store both workgroup sizes (256- and
+ * 128-column tiles) and both tile orders; or STENCIL_OP_HDIFF,
  * timed in the damping form: only the generalised diffusion's hdiff has a
  * tile; the other ops have none to choose: STENCIL_E_ARG) on a domain of this size (scratch
  * fields allocated and freed by the library for the duration of the call,

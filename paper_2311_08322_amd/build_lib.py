@@ -45,6 +45,11 @@ def _units():
                        *(["-DGT4MI_SPLIT_LONG"] if t == "double" else []), *UNROLL]))
             u.append(("k_step_inst.hip", f"splitvar_{t}_{ti}",
                       [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", "-DGT4MI_VAR", *UNROLL]))
+            # 128-column tiles (256-lane workgroups) of the two-ended step
+            for var in ([], ["-DGT4MI_VAR"]):
+                u.append(("k_step_inst.hip", f"split{'var' if var else ''}128_{t}_{ti}",
+                          [f"-DGT4MI_T={t}", f"-DGT4MI_TI={ti}", "-DGT4MI_SPLIT", "-DGT4MI_SPLIT_NT=128", *var,
+                           *UNROLL]))
         for col in cols:
             u.append(("k_step_inst.hip", f"vadv_{t}_c{col}",
                       [f"-DGT4MI_T={t}", "-DGT4MI_VADV", f"-DGT4MI_COL={col}", *UNROLL]))

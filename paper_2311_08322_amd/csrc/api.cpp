@@ -141,12 +141,20 @@ int check_no_alias(const char* oname, Span o, const char* iname, Span in) {
 }
 
 // ------------------------------------------------------------------ options
+// Whether a 128-column tile can run: the fused two-ended step only.
+static bool narrow_tile_runs(const ResolvedOpts& r, int op, stencil_dtype dt, const int64_t* dom) {
+  return op == STENCIL_OP_STEP && r.impl != STENCIL_IMPL_PLAIN && r.column_store == STENCIL_COLUMN_SPLIT &&
+         dom[2] <= split_step_limit((int)esize(dt));
+}
+
 ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, const int64_t* dom) {
   ResolvedOpts r;
   r.impl = o ? o->impl : STENCIL_IMPL_AUTO;
   int32_t ti = 0, tj = 0, col = 0, ord = 0;
   tuning_get(dt, op, dom, &ti, &tj, &col, &ord);
-  r.tile_i = (o && o->tile_i) ? o->tile_i : ti;
+  const bool own_tile = o && o->tile_i;
+  r.tile_i = own_tile ? o->tile_i : ti;
+  r.tile_j = own_tile ? (o->tile_j ? o->tile_j : kWG / o->tile_i) : tj;
   r.column_store = (o && o->column_store) ? o->column_store : col;
   if (r.column_store == STENCIL_COLUMN_AUTO) {
     if (op == STENCIL_OP_STEP && dom[2] <= split_step_limit((int)esize(dt)))
@@ -154,6 +162,10 @@ ResolvedOpts resolve_opts(const stencil_options* o, stencil_dtype dt, int op, co
     else
       r.column_store = (dt == STENCIL_F64 && dom[2] > 96) ? STENCIL_COLUMN_OUTBUF : STENCIL_COLUMN_REGISTERS;
   }
+  // a tuned 128-column tile where the call does not run the two-ended step
+  // (another column store, or columns past its limit) takes the 256-column
+  // tile of the same width; a caller's own such tile is refused by the step
+  if (!own_tile && !narrow_tile_runs(r, op, dt, dom)) r.tile_j = kWG / r.tile_i;
   r.ws = o ? o->workspace : nullptr;
   r.ws_bytes = o ? o->workspace_bytes : 0;
   r.form = o ? o->hdiff_form : STENCIL_HDIFF_STATED;
@@ -167,11 +179,10 @@ int check_opts(const stencil_options* o) {
   if (!o) return STENCIL_OK;
   if (o->impl < STENCIL_IMPL_AUTO || o->impl > STENCIL_IMPL_PLAIN)
     return fail(STENCIL_E_ARG, "options.impl = %d unknown", (int)o->impl);
-  if (o->tile_i != 0 && !(o->tile_i == 64 && (o->tile_j == 4 || o->tile_j == 0)) &&
-      !(o->tile_i == 32 && (o->tile_j == 8 || o->tile_j == 0)) &&
-      !(o->tile_i == 16 && (o->tile_j == 16 || o->tile_j == 0)))
-    return fail(STENCIL_E_ARG, "options tile %dx%d unsupported (64x4, 32x8, 16x16)", (int)o->tile_i,
-                (int)o->tile_j);
+  if (o->tile_i != 0 && !(o->tile_j == 0 && (o->tile_i == 64 || o->tile_i == 32 || o->tile_i == 16)) &&
+      !tile_wide(o->tile_i, o->tile_j) && !tile_narrow(o->tile_i, o->tile_j))
+    return fail(STENCIL_E_ARG, "options tile %dx%d unsupported (64x4, 32x8, 16x16; 64x2, 32x4, 16x8)",
+                (int)o->tile_i, (int)o->tile_j);
   if (o->column_store < 0 || o->column_store > STENCIL_COLUMN_SPLIT)
     return fail(STENCIL_E_ARG, "options.column_store = %d unknown", (int)o->column_store);
   if (o->workspace_bytes && !o->workspace) return fail(STENCIL_E_NULL, "options.workspace is NULL");
@@ -341,7 +352,7 @@ int run_step(const stencil_field* u, const stencil_field* data, const stencil_fi
   StepArgs<T> A = step_args<T>(u, data, w, out, dom, coeff, dt_dz, mask);
   apply_variant(A, r);
   A.order = r.order;
-  return hip_status(launch_step_fused<T>(A, r.tile_i, r.column_store, s), "step (fused)");
+  return hip_status(launch_step_fused<T>(A, r.tile_i, r.tile_j, r.column_store, s), "step (fused)");
 }
 
 template <typename T>
@@ -520,6 +531,10 @@ int stencil_step(stencil_dtype dtype, const stencil_field* u, const stencil_fiel
                   split_step_limit((int)es), (long long)domain[2]);
   }
   TRY(fused_nk_ok(r, domain));
+  if (tile_narrow(r.tile_i, r.tile_j) && !narrow_tile_runs(r, STENCIL_OP_STEP, dtype, domain))
+    return fail(STENCIL_E_UNSUPPORTED,
+                "the %dx%d tile (128 columns) runs the fused two-ended step only (column store SPLIT, nk <= %d)",
+                r.tile_i, r.tile_j, split_step_limit((int)es));
   if (r.impl == STENCIL_IMPL_PLAIN) TRY(need_plain_ws(r, plain_ws_bytes(es, domain)));
   TRY(check_device());
   TRY(dtype == STENCIL_F64 ? run_step<double>(u, data, w, out, domain, coeff, dt_dz, mask, r, stream)

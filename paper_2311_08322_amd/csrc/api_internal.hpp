@@ -40,7 +40,7 @@ int check_field(const char* name, const stencil_field* f, const int64_t* dom, Ro
 
 struct ResolvedOpts {
   int impl;
-  int tile_i;
+  int tile_i, tile_j;
   int column_store;
   void* ws;
   size_t ws_bytes;
@@ -48,6 +48,11 @@ struct ResolvedOpts {
   const stencil_field* kappa;  // per-point coefficient or null
   int order;                   // stencil_tile_order (resolved: XCD or DISPATCH)
 };
+// Tile shapes of the fused forward kernels: 256 columns (64x4, 32x8,
+// 16x16: 512-lane workgroups in the two-ended step) or, in the two-ended
+// step only, 128 columns (64x2, 32x4, 16x8: 256-lane workgroups).
+inline bool tile_wide(int ti, int tj) { return (ti == 64 && tj == 4) || (ti == 32 && tj == 8) || (ti == 16 && tj == 16); }
+inline bool tile_narrow(int ti, int tj) { return (ti == 64 && tj == 2) || (ti == 32 && tj == 4) || (ti == 16 && tj == 8); }
 // options that ask for the generalised diffusion
 inline bool variant_opts(const stencil_options* o) {
   return o && (o->hdiff_form != STENCIL_HDIFF_STATED || o->coeff_field != nullptr);

@@ -11,8 +11,22 @@ static hipError_t step_by_tile(const StepArgs<T>& A, int tile_i, hipStream_t s) 
   return launch_step_classes<T, 16, 16, COL>(A, s);
 }
 
+template <typename T, int NT>
+static hipError_t split_by_tile(const StepArgs<T>& A, int tile_i, bool var, hipStream_t s) {
+  if (var) {
+    if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, true>(A, s);
+    if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, true>(A, s);
+    return launch_split_classes<T, 16, NT / 16, true>(A, s);
+  }
+  if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, false>(A, s);
+  if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, false>(A, s);
+  return launch_split_classes<T, 16, NT / 16, false>(A, s);
+}
+
+// tile_j: with tile_i, the tile of the two-ended step (tile_i * tile_j = 256
+// or 128 columns); the one-lane kernels take tile_i x (256 / tile_i)
 template <typename T>
-hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) {
+hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int tile_j, int col, hipStream_t s) {
   const bool var = A.kappa != nullptr || A.form != 0;  // the generalised diffusion: two-ended step only
   if (var || (col == 3 && A.nk <= split_step_limit(sizeof(T)))) {  // STENCIL_COLUMN_SPLIT
     if (A.nk > split_step_limit(sizeof(T))) return hipErrorInvalidValue;
@@ -26,18 +40,11 @@ hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int col, hipStream_t s) 
         return launch_split_long<T, 16>(A, s);
       }
     }
-    constexpr int NT = GT4MI_SPLIT_NT;
-    const int tj = NT / tile_i;
+    const bool narrow = tile_i * tile_j == 128;
+    const int tj = (narrow ? 128 : 256) / tile_i;
     A.tiles_i = (A.ni + tile_i - 1) / tile_i;
     A.ntiles = A.tiles_i * ((A.nj + tj - 1) / tj);
-    if (var) {
-      if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, true>(A, s);
-      if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, true>(A, s);
-      return launch_split_classes<T, 16, NT / 16, true>(A, s);
-    }
-    if (tile_i == 64) return launch_split_classes<T, 64, NT / 64, false>(A, s);
-    if (tile_i == 32) return launch_split_classes<T, 32, NT / 32, false>(A, s);
-    return launch_split_classes<T, 16, NT / 16, false>(A, s);
+    return narrow ? split_by_tile<T, 128>(A, tile_i, var, s) : split_by_tile<T, 256>(A, tile_i, var, s);
   }
   const int tj = kWG / tile_i;
   A.tiles_i = (A.ni + tile_i - 1) / tile_i;
@@ -66,8 +73,8 @@ hipError_t launch_vadv_fused(StepArgs<T> A, hipStream_t s) {
   }
 }
 
-template hipError_t launch_step_fused<float>(StepArgs<float>, int, int, hipStream_t);
-template hipError_t launch_step_fused<double>(StepArgs<double>, int, int, hipStream_t);
+template hipError_t launch_step_fused<float>(StepArgs<float>, int, int, int, hipStream_t);
+template hipError_t launch_step_fused<double>(StepArgs<double>, int, int, int, hipStream_t);
 template hipError_t launch_vadv_fused<float>(StepArgs<float>, hipStream_t);
 template hipError_t launch_vadv_fused<double>(StepArgs<double>, hipStream_t);
 

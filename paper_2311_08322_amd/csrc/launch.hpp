@@ -13,7 +13,7 @@ constexpr int kMaxFusedNk = 160;
 // fused forward (k_step.hip dispatches; k_step_inst.hip instantiates the
 // register classes of each dtype / tile / column store)
 template <typename T>
-hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int column_store, hipStream_t s);
+hipError_t launch_step_fused(StepArgs<T> A, int tile_i, int tile_j, int column_store, hipStream_t s);
 template <typename T, int TI, int TJ, int COL>
 hipError_t launch_step_classes(const StepArgs<T>& A, hipStream_t s);
 template <typename T, int COL>
@@ -29,9 +29,10 @@ hipError_t launch_split_long(const StepArgs<T>& A, hipStream_t s);
 template <typename T, bool ADJ>
 hipError_t launch_column_split_classes(StepArgs<T> A, hipStream_t s);
 constexpr int column_split_limit(int elem_bytes) { return elem_bytes == 8 ? 144 : 160; }
-// Columns per tile of the two-ended fused step (two lanes per column): 256
-// makes 512-lane workgroups, 128 makes 256-lane ones, of which two fit a CU
-// at the register use of the longer classes.
+// Columns per tile of the two-ended fused step (two lanes per column) in one
+// compilation of k_step_inst.hip: 256 makes 512-lane workgroups, 128 makes
+// 256-lane ones; both are built and the tile option (a tuned dimension)
+// picks one.
 #ifndef GT4MI_SPLIT_NT
 #define GT4MI_SPLIT_NT 256
 #endif

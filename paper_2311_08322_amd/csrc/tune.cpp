@@ -126,9 +126,11 @@ int tune_candidates(stencil_dtype dtype, int op, const stencil_field* u, const s
   std::vector<Cand> cands;
   for (int t : {64, 32, 16}) {
     if (op == STENCIL_OP_STEP) {
+      // the two-ended step in both workgroup sizes (256- and 128-column tiles)
       if (nk <= split_step_limit((int)(dtype == STENCIL_F64 ? 8 : 4)))
-        for (int ord : {STENCIL_ORDER_XCD, STENCIL_ORDER_DISPATCH})
-          cands.push_back({t, 256 / t, STENCIL_COLUMN_SPLIT, ord});
+        for (int nt : {256, 128})
+          for (int ord : {STENCIL_ORDER_XCD, STENCIL_ORDER_DISPATCH})
+            cands.push_back({t, nt / t, STENCIL_COLUMN_SPLIT, ord});
       if (dtype == STENCIL_F32 || nk <= 96) cands.push_back({t, 256 / t, STENCIL_COLUMN_REGISTERS, STENCIL_ORDER_XCD});
       if (dtype == STENCIL_F64) cands.push_back({t, 256 / t, STENCIL_COLUMN_OUTBUF, STENCIL_ORDER_XCD});
     } else {
@@ -351,8 +353,7 @@ int stencil_load_tuning(const char* path) {
         !read_int(p, e, "tile_i", &v.tile_i) || !read_int(p, e, "tile_j", &v.tile_j) ||
         !read_int(p, e, "column_store", &v.col))
       return fail(STENCIL_E_ARG, "%s: malformed entry", path);
-    if (!((v.tile_i == 64 && v.tile_j == 4) || (v.tile_i == 32 && v.tile_j == 8) ||
-          (v.tile_i == 16 && v.tile_j == 16)) ||
+    if (!(tile_wide(v.tile_i, v.tile_j) || (tile_narrow(v.tile_i, v.tile_j) && v.col == STENCIL_COLUMN_SPLIT)) ||
         v.col < 0 || v.col > STENCIL_COLUMN_SPLIT)
       return fail(STENCIL_E_ARG, "%s: entry with unsupported tile or column store", path);
     if (read_int(p, e, "tile_order", &v.order) &&

@@ -188,6 +188,16 @@ def test_options(L):
     o = _lib.StencilOptions()
     o.tile_i, o.tile_j = 48, 4
     assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    o.tile_i, o.tile_j = 64, 8  # neither 256 nor 128 columns
+    assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_ARG")
+    # 128-column tiles run the two-ended step only
+    for ti, tj in ((64, 2), (32, 4), (16, 8)):
+        o = _lib.StencilOptions()
+        o.tile_i, o.tile_j, o.column_store = ti, tj, _lib.COLUMN_REGISTERS
+        assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_UNSUPPORTED")
+        assert "two-ended" in _lib.last_error()
+        o.column_store = _lib.COLUMN_SPLIT  # accepted: fails later, at the device check
+        assert step(L, u, data, w, out, d, opts=o) not in (code("STENCIL_E_ARG"), code("STENCIL_E_UNSUPPORTED"))
     o = _lib.StencilOptions()
     o.impl = _lib.IMPL_PLAIN  # no workspace
     assert step(L, u, data, w, out, d, opts=o) == code("STENCIL_E_WORKSPACE")
@@ -294,6 +304,14 @@ def test_tuning_json_roundtrip(L, tmp_path):
     bad.write_text('{"arch": "gfx950", "entries": [{"dtype": 1, "op": 2, "tile_i": 48}]}')
     assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
     doc["entries"][0]["tile_order"] = 7
+    bad.write_text(json.dumps(doc))
+    assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
+    # a 128-column tile is a two-ended step entry only
+    doc["entries"][0].update(tile_order=_lib.ORDER_XCD, tile_i=32, tile_j=4, column_store=3)
+    p.write_text(json.dumps(doc))
+    assert L.stencil_load_tuning(str(p).encode()) == 0
+    assert look(d) == 0 and (ti.value, tj.value, col.value) == (32, 4, 3)
+    doc["entries"][0]["column_store"] = 1
     bad.write_text(json.dumps(doc))
     assert L.stencil_load_tuning(str(bad).encode()) == code("STENCIL_E_ARG")
     assert L.stencil_load_tuning(b"/nonexistent/x.json") == code("STENCIL_E_ARG")

@@ -158,6 +158,38 @@ def test_step(dims, impl, tile, col, order, dtype):
     assert np.all(full[ring] == -3.0)
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("tile", [64, 32, 16])
+@pytest.mark.parametrize("dims", [(100, 37, 80), (67, 45, 7), (1, 1, 1), (30, 70, 79), (33, 17, 137),
+                                  (21, 13, 144), (45, 21, 88)], ids=lambda d: "x".join(map(str, d)))
+def test_step_128_column_tiles(dims, tile, dtype):
+    """The two-ended step in 128-column tiles (256-lane workgroups): the
+    oracle's values, its masks bit for bit, and the same bits as the
+    256-column tile of the same width."""
+    ni, nj, nk = dims
+    if nk > api.stencil_max_fused_nk(api.F64 if dtype == torch.float64 else api.F32):
+        pytest.skip("longer than the fused classes")
+    print(f"step 128-column tiles {dims} tile {tile}x{128 // tile} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=107)
+    r = _ref_inputs(f, dtype)
+    u, data, w = dev_fields(f, dtype, DEV)
+    res = {}
+    for tj in (128 // tile, 256 // tile):
+        out = fields.alloc(ni, nj, nk, dtype, DEV, fill=-3.0)
+        mask = fields.mask_tensor(dims, DEV)
+        o = api.Options(impl=api.IMPL_FUSED, tile_i=tile, tile_j=tj, column_store=api.COLUMN_SPLIT)
+        api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask, opts=o)
+        torch.cuda.synchronize()
+        res[tj] = (fields.padded(out, ni, nj, nk).clone(), mask.clone())
+    a, b = res[128 // tile], res[256 // tile]
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    ref, mx, my = orc.step(r.u, r.data, r.w, c_scalar(inputs.COEFF, dtype), inputs.DT_DZ,
+                           decide_f32=(dtype == torch.float32))
+    assert rel_err(host(a[0][:, 2:-2, 2:-2]), ref[:, 2:-2, 2:-2]) <= TOL[dtype]
+    gmx, gmy = unpack_mask(a[1], ni, nj, nk)
+    assert np.array_equal(gmx, mx) and np.array_equal(gmy, my)
+
+
 def test_step_unaligned_and_strided_layouts():
     """Fields with different pitches, origins and an offset vertical interval."""
     ni, nj, nk = 77, 23, 19
@@ -263,7 +295,8 @@ def test_autotune_step_and_tuned_step(dtype):
     best = api.stencil_autotune(dtype, api.OP_STEP, dims, reps=2)
     assert best > 0
     ti, tj, col, order = api.stencil_tuning_lookup(dtype, api.OP_STEP, dims)
-    assert (ti, tj) in ((64, 4), (32, 8), (16, 16))
+    assert (ti, tj) in ((64, 4), (32, 8), (16, 16)) or ((ti, tj) in ((64, 2), (32, 4), (16, 8)) and
+                                                        col == api.COLUMN_SPLIT)
     assert col in (api.COLUMN_REGISTERS, api.COLUMN_OUTBUF, api.COLUMN_SPLIT)
     assert order in (api.ORDER_XCD, api.ORDER_DISPATCH)
     f = inputs.fields_sized(*dims, seed=108)
@@ -291,7 +324,8 @@ def test_autotune_on_fields_then_step():
     assert api.stencil_autotune_fields(u, data, w, scratch, dims, reps=2) > 0
     assert torch.equal(u.tensor, u0)
     ti, tj, col, order = api.stencil_tuning_lookup(torch.float64, api.OP_STEP, dims)
-    assert (ti, tj) in ((64, 4), (32, 8), (16, 16)) and order in (api.ORDER_XCD, api.ORDER_DISPATCH)
+    assert ((ti, tj) in ((64, 4), (32, 8), (16, 16)) or (ti, tj) in ((64, 2), (32, 4), (16, 8))) and \
+        order in (api.ORDER_XCD, api.ORDER_DISPATCH)
     out = fields.alloc(*dims, torch.float64, DEV, fill=0.0)
     api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ)
     torch.cuda.synchronize()
