@@ -315,7 +315,7 @@ def main():
         # this size class on the very buffers the graph will step (where the
         # fields sit in memory matters as well as their shape)
         print(f"bench: autotuning the fused step ({dtype}) on its fields", file=sys.stderr, flush=True)
-        api.stencil_autotune_fields(u_a, data, w, u_b, dims, reps=3, stream=s)
+        api.stencil_autotune_fields(u_a, data, w, u_b, dims, reps=10, stream=s)
         tuned["f64" if dtype == torch.float64 else "f32"] = api.stencil_tuning_lookup(dtype, api.OP_STEP, dims)
         for n in range(W):  # eager warm-up steps
             src, dst = (u_a, u_b) if n % 2 == 0 else (u_b, u_a)

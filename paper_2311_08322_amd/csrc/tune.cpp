@@ -142,7 +142,9 @@ int tune_candidates(stencil_dtype dtype, int op, const stencil_field* u, const s
   (void)hipEventCreate(&e1);
   double best = 1e300;
   Cand bc = cands[0];
-  for (const Cand& c : cands) {
+  // The candidate's median window time after warm_us of device time spent
+  // in warm-up windows.
+  auto measure = [&](const Cand& c, double warm_us, double* out_us) -> int {
     stencil_options o;
     memset(&o, 0, sizeof o);
     o.impl = STENCIL_IMPL_FUSED;
@@ -173,22 +175,31 @@ int tune_candidates(stencil_dtype dtype, int op, const stencil_field* u, const s
       *us = 1000.0 * ms / reps;
       return STENCIL_OK;
     };
-    // Warm-up: after a change of candidate the calls run measurably slower
-    // for several milliseconds (the caches, the last-level one included,
-    // still hold what the previous order left), so windows run until at
-    // least 10 ms of device time has passed; then the median of three
-    // windows counts.
     double us = 0.0, warm = 0.0;
-    for (int n = 0; n < 256 && warm < 10000.0 && !rc; ++n) {
-      rc = window(&us);
+    for (int n = 0; n < 1024 && warm < warm_us; ++n) {
+      TRY(window(&us));
       warm += us * reps;
     }
+    double t5[5];
+    for (int n = 0; n < 5; ++n) TRY(window(&t5[n]));
+    std::sort(t5, t5 + 5);
+    *out_us = t5[2];
+    return STENCIL_OK;
+  };
+  // Device warm-up before the first measurement: a device that has been
+  // idle runs its first tens of milliseconds of work slower, which would
+  // favour the candidates timed last.
+  double ignored = 0.0;
+  rc = measure(cands[0], 100000.0, &ignored);
+  for (const Cand& c : cands) {
     if (rc) break;
-    double t3[3];
-    for (int n = 0; n < 3 && !rc; ++n) rc = window(&t3[n]);
+    // After a change of candidate the calls run measurably slower for
+    // several milliseconds (the caches, the last-level one included, still
+    // hold what the previous order left): at least 10 ms of warm-up, then
+    // the median of five windows (candidates often differ by 1-3%).
+    double us = 0.0;
+    rc = measure(c, 10000.0, &us);
     if (rc) break;
-    std::sort(t3, t3 + 3);
-    us = t3[1];
     if (us < best) {
       best = us;
       bc = c;
