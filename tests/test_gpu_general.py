@@ -87,6 +87,35 @@ def test_step_general(dims, form, field, dtype):
     assert np.array_equal(gx, mx) and np.array_equal(gy, my)
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=IDS)
+@pytest.mark.parametrize("tile", [64, 32, 16])
+def test_step_general_128_column_tiles(tile, dtype):
+    """The generalised step (damping form, coefficient field) in 128-column
+    tiles equals the 256-column tiles bit for bit, masks included, and the
+    oracle."""
+    dims = (67, 45, 33)
+    ni, nj, nk = dims
+    print(f"general step 128-column tiles {tile}x{128 // tile} {dtype}", flush=True)
+    f = inputs.fields_sized(ni, nj, nk, seed=603)
+    k, kd = _kappa(dims, dtype, True)
+    u, data, w = dev_fields(f, dtype, DEV)
+    res = {}
+    for tj in (128 // tile, 256 // tile):
+        out = fields.alloc(ni, nj, nk, dtype, DEV, fill=-3.0)
+        mask = fields.mask_tensor(dims, DEV)
+        o = _opts(api.HDIFF_DAMPING, kd, tile_i=tile, tile_j=tj)
+        api.stencil_step(u, data, w, out, dims, inputs.COEFF, inputs.DT_DZ, mask=mask, opts=o)
+        torch.cuda.synchronize()
+        res[tj] = (fields.padded(out, ni, nj, nk).clone(), mask.clone())
+    a, b = res[128 // tile], res[256 // tile]
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    nxt, mx, my = orc.step(_r(f.u, dtype), _r(f.data, dtype), _r(f.w, dtype), c_scalar(inputs.COEFF, dtype),
+                           inputs.DT_DZ, decide_f32=(dtype == torch.float32), kappa=_r(k, dtype), damping=True)
+    assert rel_err(host(a[0][:, 2:-2, 2:-2]), nxt[:, 2:-2, 2:-2]) <= TOL[dtype]
+    gx, gy = unpack_mask(a[1], ni, nj, nk)
+    assert np.array_equal(gx, mx) and np.array_equal(gy, my)
+
+
 def test_step_general_full_size():
     """512 x 512 x 80 FP64, damping form with a coefficient field."""
     dims = (512, 512, 80)
