@@ -270,6 +270,8 @@ def main():
                     help="with --only-step: also time the step written in the stencil language")
     ap.add_argument("--with-adjoint", action="store_true",
                     help="with --only-step: also run the step adjoint a few times (counter collection)")
+    ap.add_argument("--with-f32", action="store_true",
+                    help="with --only-step: also run the FP32 step of every tile (counter collection)")
     ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only time a plain device copy of this many MiB (counter calibration)")
@@ -410,13 +412,21 @@ def main():
         # a few eager launches of the step kernel of every tile (the tuned
         # one among them): counter collection sees dispatches outside graph
         # replays, and every tile the tuner may pick gets measured
-        u_a, u_b, data, w = mkfields(torch.float64)
-        for tile in (64, 32, 16):
-            for nt in (256, 128):  # both workgroup sizes
-                for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
-                    o = api.Options(tile_i=tile, tile_j=nt // tile, column_store=api.COLUMN_SPLIT, tile_order=order)
-                    for n in range(3):
-                        api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
+        def every_tile(dtype):
+            u_a, u_b, data, w = mkfields(dtype)
+            for tile in (64, 32, 16):
+                for nt in (256, 128):  # both workgroup sizes
+                    for order in (api.ORDER_XCD, api.ORDER_DISPATCH):
+                        o = api.Options(tile_i=tile, tile_j=nt // tile, column_store=api.COLUMN_SPLIT,
+                                        tile_order=order)
+                        for n in range(3):
+                            api.stencil_step(u_a, data, w, u_b, dims, inputs.COEFF, inputs.DT_DZ, opts=o)
+            return u_a, u_b, data, w
+
+        if args.with_f32:
+            every_tile(torch.float32)
+            torch.cuda.synchronize()
+        u_a, u_b, data, w = every_tile(torch.float64)
         if args.with_adjoint:
             # the step adjoint (column adjoint + gather) on the forward's mask
             mask = fields.mask_tensor(dims, dev)
