@@ -272,7 +272,7 @@ def main():
                     help="with --only-step: also run the step adjoint a few times (counter collection)")
     ap.add_argument("--with-f32", action="store_true",
                     help="with --only-step: also run the FP32 step of every tile (counter collection)")
-    ap.add_argument("--reps", type=int, default=5, help="graph replays for the median")
+    ap.add_argument("--reps", type=int, default=10, help="graph replays for the median")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only time a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
