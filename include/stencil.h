@@ -55,7 +55,15 @@ extern "C" {
 #define STENCIL_ABI_VERSION 3
 #define STENCIL_HALO 2
 
-typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype;
+/* Element type.  The two range markers are not dtypes: they make every 32-bit
+   value a value of the type, so that an unknown dtype passed by a caller is
+   well defined in C++ and rejected with STENCIL_E_DTYPE. */
+typedef enum {
+  STENCIL_F32 = 0,
+  STENCIL_F64 = 1,
+  STENCIL_DTYPE_RANGE_MIN_ = -2147483647 - 1,
+  STENCIL_DTYPE_RANGE_MAX_ = 2147483647
+} stencil_dtype;
 
 enum {
   STENCIL_OK = 0,
