@@ -555,3 +555,19 @@ def test_openmp_build_is_identical_to_serial(oracle):
             assert np.array_equal(x, y)
     for x, y in zip(ser_adj, par_adj):
         assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------------------- the NumPy-backend analogue
+@pytest.mark.parametrize("dims", [(1, 1, 1), (6, 5, 3), (17, 9, 2), (33, 20, 13), (64, 48, 16)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_numpy_step_equals_oracle(oracle, dims):
+    # the whole-array NumPy step (CPU context for the benchmark) is the
+    # oracle's step bit for bit, halo included
+    from oracle import numpy_step
+
+    ni, nj, nk = dims
+    f = inputs.fields_sized(ni, nj, nk, seed=60 + nk)
+    ref, _, _ = oracle.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    got = numpy_step.step(f.u, f.data, f.w, COEFF, DT_DZ)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
