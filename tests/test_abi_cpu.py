@@ -110,7 +110,8 @@ def test_null_and_dtype(L):
     u, data, w, out, d = fields()
     assert step(L, None, data, w, out, d) == code("STENCIL_E_NULL")
     assert "u" in _lib.last_error()
-    assert step(L, u, data, w, out, d, dt=7) == code("STENCIL_E_DTYPE")
+    for dt in (7, -1, 2, -2147483648, 2147483647):  # every 32-bit value is a valid argument
+        assert step(L, u, data, w, out, d, dt=dt) == code("STENCIL_E_DTYPE")
     u.data = None
     assert step(L, u, data, w, out, d) == code("STENCIL_E_NULL")
     u, data, w, out, d = fields()
