@@ -18,7 +18,10 @@ two benchmark stencils of Sec. 3.1 at the sizes below):
 * a per-point coefficient field (the generalised diffusion) is drawn
   ``U[coeff/2, 3 coeff/2)`` on the interior from child 103;
 * the batched workload draws 32 (ni, nj, nk) triples, integers uniform and
-  inclusive in [48,384] x [48,384] x [40,137], then one child per field.
+  inclusive in [48,384] x [48,384] x [40,137], then one child per field;
+* domains too large for host arrays (levels beyond 2 GiB) are drawn on the
+  device by torch's generator, seeded from child 104 (fields, the same
+  ranges) and 105 (cotangent), in the fields' own precision.
 
 Arrays are returned in the layout (k, j, i) with i fastest.
 """
@@ -51,6 +54,8 @@ ADJ_256 = Workload("step adjoint 256x256x80", 256, 256, 80, 4)
 BATCH_CHILD = 5
 BATCH_FIELDS = 32
 BATCH_RANGE = ((48, 384), (48, 384), (40, 137))
+
+LARGE_CHILD = 104  # fields drawn on the device (domains too large for host arrays)
 
 COTANGENT_CHILD = 100
 DOT_CHILD = 101
@@ -142,3 +147,27 @@ def batch_fields(n: int = BATCH_FIELDS):
 
 def as_f32(a: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _torch_seed(child: int) -> int:
+    return int(np.random.SeedSequence([ROOT_SEED, child]).generate_state(1, np.uint64)[0] >> 1)
+
+
+def fill_device(views, ranges, child: int) -> None:
+    """Fills device tensors (views allowed) in order, view n uniform on
+    ranges[n] = (lo, hi), from torch's generator on their device seeded from
+    the child's SeedSequence: for domains whose arrays are too large to draw
+    on the host.  The values are drawn in the views' own precision; a CPU
+    check reads back the values actually stored, so both sides see the same
+    inputs."""
+    import torch
+
+    g = torch.Generator(device=views[0].device)
+    g.manual_seed(_torch_seed(child))
+    for v, (lo, hi) in zip(views, ranges):
+        v.uniform_(lo, hi, generator=g)
+
+
+# the ranges of u, w and data (as draw_fields) and of a cotangent
+FIELD_RANGES = ((0.0, 1.0), (-1.0, 1.0), (-0.1, 0.1))
+COTANGENT_RANGE = (-1.0, 1.0)
